@@ -1,0 +1,153 @@
+/*
+ * iwpp.h -- C ABI of the MI355X (gfx950) irregular wavefront propagation library.
+ *
+ * Two instances of the irregular wavefront propagation pattern (IWPP) of
+ * Teodoro et al., "Efficient Irregular Wavefront Propagation Algorithms on
+ * Hybrid CPU-GPU Machines" (arXiv 1209.3314):
+ *
+ *   - grayscale morphological reconstruction by dilation, rho_I(J)
+ *     (Sec. 2.1 and Algorithms 2 and 5), 4- or 8-connected;
+ *   - the propagation-based Euclidean distance transform that carries the
+ *     nearest feature of every pixel (Sec. 2.2 and Algorithms 3 and 6).
+ *
+ * Every symbol is extern "C"; no C++ type or exception crosses this boundary
+ * and the library never aborts the process.
+ *
+ * Memory.  Image arguments are DEVICE pointers on the context's device, owned
+ * by the caller, row-major with row stride == width (contiguous).  The context
+ * owns its scratch memory (queues, keys, counters), which it grows on demand
+ * and frees in iwpp_destroy.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Compute calls only enqueue work on it and return; results are
+ * valid once the stream has been synchronised.  A context serves one call at a
+ * time: calls on one context must not overlap (their scratch is shared), so
+ * either use one stream per context or order the calls.
+ *
+ * Errors.  Argument errors return IWPP_EINVAL before anything is enqueued; a
+ * HIP error from a launch returns IWPP_EDEVICE.  A device-side failure (a
+ * safety limit hit inside a kernel) is reported by iwpp_get_stats through the
+ * `status` field.  iwpp_last_error gives a message for the last non-OK status.
+ */
+#ifndef IWPP_H
+#define IWPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct iwpp_ctx iwpp_ctx;
+
+typedef enum {
+  IWPP_OK = 0,
+  IWPP_EINVAL = -1,  /* bad argument: nothing was enqueued */
+  IWPP_ENOMEM = -2,  /* scratch allocation failed */
+  IWPP_EDEVICE = -3, /* HIP launch/runtime error, or a device-side failure */
+  IWPP_EBUSY = -4    /* the operation needs an idle context */
+} iwpp_status;
+
+/* Tunables.  Zero means "library default" for every field.  None of them can
+ * change a result: reconstruction is unique (Sec. 2.1) and the distance
+ * transform follows fixed round semantics, so every setting yields the same
+ * bytes; they only change speed (and, for the capacity, force the overflow
+ * path of Sec. 3.2 so it can be tested). */
+typedef struct {
+  /* Capacity, in tiles, of each round's work list of the reconstruction
+   * propagation.  When a round needs more, the excess is dropped, a flag is
+   * raised and the work list is rebuilt from the current image by a dense
+   * seed detection, as the paper re-runs propagation from its partial output
+   * after its global queue overflows (Sec. 3.2, Sec. 5.2.4).  0 = no limit. */
+  int64_t mr_list_capacity;
+  /* Cap on sweep iterations per tile visit before the tile is re-queued. */
+  int32_t mr_max_sweeps;
+  /* Workgroups of the persistent kernels (0 = fill the device). */
+  int32_t persistent_blocks;
+  int32_t reserved[8];
+} iwpp_options;
+
+/* Counters of the last compute call on a context (see iwpp_get_stats). */
+typedef struct {
+  int32_t status;            /* IWPP_OK, or IWPP_EDEVICE if a kernel hit a safety limit */
+  int32_t op;                /* 1 = reconstruction, 2 = distance transform */
+  int64_t seeds;             /* MR: pixels meeting the seed condition of Alg. 5 after the seed pass;
+                                EDT: contour features (initial frontier) */
+  int64_t items;             /* MR: tile visits in propagation; EDT: frontier items over all rounds */
+  int64_t sweeps;            /* MR: sweep iterations over all tile visits */
+  int64_t rounds;            /* MR: propagation rounds; EDT: rounds that changed a pixel */
+  int64_t updates;           /* EDT: successful key improvements */
+  int64_t overflow_restarts; /* MR: dense re-seeds after a work-list overflow */
+  int64_t reserved[6];
+} iwpp_stats;
+
+/* Library version, (major << 16) | minor. */
+int32_t iwpp_version(void);
+
+/* Create a context on HIP device `device`.  `opt` may be NULL.  On success
+ * *out receives the context.  Errors: IWPP_EINVAL (bad device, NULL out),
+ * IWPP_EDEVICE. */
+int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out);
+
+/* Free a context and its scratch memory.  NULL is allowed.  Waits for the
+ * context's work to finish first. */
+void iwpp_destroy(iwpp_ctx* ctx);
+
+/* Message for the last non-OK status on `ctx` (or for iwpp_create when ctx is
+ * NULL).  The pointer stays valid until the next call on the context. */
+const char* iwpp_last_error(const iwpp_ctx* ctx);
+
+/* Grayscale morphological reconstruction by dilation of mask I from marker J,
+ * rho_I(J): the limit of J(p) <- max{J(q) : q in N_G(p) U {p}} ^ I(p) applied
+ * until nothing changes (Sec. 2.1), computed as Algorithm 5 does: a seed pass
+ * of scans, seed detection over the full neighbourhood, and queue-driven
+ * propagation with atomic max updates.
+ *
+ *   marker, mask : const uint8_t[height*width] (device)
+ *   out          : uint8_t[height*width] (device); may alias marker (in place),
+ *                  must not alias mask
+ *   height,width : >= 1
+ *   conn         : 4 or 8
+ * A marker above the mask is clamped first (the result is rho_I(min(J, I))).
+ * Pixels outside the image are not neighbours.  The result is unique, so it is
+ * bit-exact whatever the schedule.
+ * Errors: IWPP_EINVAL (NULL pointer, dims < 1, conn not 4/8, out aliasing
+ * mask), IWPP_ENOMEM, IWPP_EDEVICE. */
+int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
+                            int32_t height, int32_t width, int32_t conn, void* stream);
+
+/* Euclidean distance transform by propagation of the nearest feature
+ * (Sec. 2.2, Algorithms 3 and 6).  Features (the paper's background, the
+ * targets of the distance) are the 0-pixels of `binary`; every pixel receives
+ * the squared distance to the feature it ends up carrying and that feature's
+ * index y*width + x.
+ *
+ * Semantics: level-synchronous rounds.  Round r offers, from every pixel that
+ * changed in round r-1 (initially the contour features), the feature that
+ * pixel held at the end of round r-1 to each in-image neighbour in N_G; a
+ * neighbour keeps the smallest (squared distance, feature index) pair.  Rounds
+ * stop when nothing changes.  These semantics make the parallel result unique
+ * (the paper's equidistant-choice argument does not hold for the propagation
+ * approximation), so the output is reproducible bit for bit.
+ *
+ *   binary        : const uint8_t[height*width] (device), 0 = feature
+ *   sqdist        : int32_t[height*width] (device), squared distance
+ *   nearest       : int32_t[height*width] (device), y*width + x of the feature
+ *   height,width  : 1 .. 32767 (so squared distances fit in int32 and the
+ *                   packed coordinates in 15 bits)
+ *   conn          : 4 or 8
+ * If the image has no feature, sqdist and nearest are -1 everywhere.
+ * Errors: IWPP_EINVAL (NULL pointer, dims out of range, conn not 4/8, outputs
+ * aliasing each other or the input), IWPP_ENOMEM, IWPP_EDEVICE. */
+int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
+                 int32_t width, int32_t conn, void* stream);
+
+/* Copy the counters of the last compute call into *out.  Synchronises with
+ * the stream of that call first.  Errors: IWPP_EINVAL (NULL), IWPP_EDEVICE. */
+int32_t iwpp_get_stats(iwpp_ctx* ctx, iwpp_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IWPP_H */

@@ -1,1 +1,169 @@
-"""MI355X-native irregular wavefront propagation (IWPP), arXiv 1209.3314."""
+"""MI355X-native irregular wavefront propagation (IWPP), after Teodoro et al.,
+"Efficient Irregular Wavefront Propagation Algorithms on Hybrid CPU-GPU
+Machines" (arXiv 1209.3314).
+
+Thin Python binding over the C ABI of ``include/iwpp.h`` (``libiwpp.so``):
+argument checks and marshalling only.  PyTorch provides the device memory and
+the stream; every step of the computation runs in the library's HIP kernels.
+There is no CPU fallback: the calls raise if the library or a GPU is missing.
+
+    morph_recon(marker, mask, conn=8, out=None) -> uint8 tensor   (Sec. 2.1)
+    edt(binary, conn=8) -> (sqdist int32, nearest int32)         (Sec. 2.2)
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+from . import _lib
+
+__all__ = ["Context", "IwppError", "morph_recon", "edt", "last_stats"]
+
+
+class IwppError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"iwpp error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _check_image(t, name: str, dtype, device=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D (height, width)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row stride == width)")
+
+
+class Context:
+    """One library context (scratch memory, counters) on one device.
+
+    Calls on a context must not overlap; the module-level functions use one
+    context per device and the current torch stream."""
+
+    def __init__(self, device: int = 0, mr_list_capacity: int = 0, mr_max_sweeps: int = 0,
+                 persistent_blocks: int = 0):
+        lib = _lib.load()
+        opt = _lib.Options()
+        opt.mr_list_capacity = int(mr_list_capacity)
+        opt.mr_max_sweeps = int(mr_max_sweeps)
+        opt.persistent_blocks = int(persistent_blocks)
+        h = ctypes.c_void_p()
+        rc = lib.iwpp_create(int(device), ctypes.byref(opt), ctypes.byref(h))
+        if rc != _lib.IWPP_OK:
+            raise IwppError(rc, lib.iwpp_last_error(None).decode())
+        self._lib = lib
+        self._h = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.iwpp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc: int):
+        raise IwppError(rc, self._lib.iwpp_last_error(self._h).decode())
+
+    def _stream(self, device):
+        return ctypes.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
+
+    def morph_recon(self, marker, mask, conn: int = 8, out=None):
+        torch = _torch()
+        _check_image(mask, "mask", torch.uint8)
+        _check_image(marker, "marker", torch.uint8, mask.device)
+        if marker.shape != mask.shape:
+            raise ValueError("marker and mask must have the same shape")
+        if conn not in (4, 8):
+            raise ValueError("conn must be 4 or 8")
+        if out is None:
+            out = torch.empty_like(mask)
+        else:
+            _check_image(out, "out", torch.uint8, mask.device)
+            if out.shape != mask.shape:
+                raise ValueError("out must have the shape of mask")
+        h, w = mask.shape
+        rc = self._lib.iwpp_morph_recon_u8(self._h, marker.data_ptr(), mask.data_ptr(), out.data_ptr(),
+                                           h, w, conn, self._stream(mask.device))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return out
+
+    def edt(self, binary, conn: int = 8, out=None):
+        torch = _torch()
+        _check_image(binary, "binary", torch.uint8)
+        if conn not in (4, 8):
+            raise ValueError("conn must be 4 or 8")
+        h, w = binary.shape
+        if out is None:
+            sq = torch.empty((h, w), dtype=torch.int32, device=binary.device)
+            nr = torch.empty((h, w), dtype=torch.int32, device=binary.device)
+        else:
+            sq, nr = out
+            _check_image(sq, "sqdist", torch.int32, binary.device)
+            _check_image(nr, "nearest", torch.int32, binary.device)
+        rc = self._lib.iwpp_edt(self._h, binary.data_ptr(), sq.data_ptr(), nr.data_ptr(), h, w, conn,
+                                self._stream(binary.device))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return sq, nr
+
+    def stats(self) -> dict:
+        st = _lib.Stats()
+        rc = self._lib.iwpp_get_stats(self._h, ctypes.byref(st))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return {"status": st.status, "op": st.op, "seeds": st.seeds, "items": st.items, "sweeps": st.sweeps,
+                "rounds": st.rounds, "updates": st.updates, "overflow_restarts": st.overflow_restarts}
+
+
+_contexts: dict = {}
+_ctx_lock = threading.Lock()
+
+
+def _default_ctx(device) -> Context:
+    idx = device.index if device.index is not None else _torch().cuda.current_device()
+    with _ctx_lock:
+        c = _contexts.get(idx)
+        if c is None:
+            c = Context(idx)
+            _contexts[idx] = c
+        return c
+
+
+def morph_recon(marker, mask, conn: int = 8, out=None):
+    """Grayscale reconstruction by dilation rho_I(J) of `mask` from `marker`
+    (uint8 GPU tensors of one shape); bit-exact."""
+    _check_image(mask, "mask", _torch().uint8)
+    return _default_ctx(mask.device).morph_recon(marker, mask, conn, out)
+
+
+def edt(binary, conn: int = 8, out=None):
+    """Propagation EDT of a uint8 GPU image (0 = feature).  Returns int32
+    (squared distance, nearest feature index y*W+x); -1 if no feature."""
+    _check_image(binary, "binary", _torch().uint8)
+    return _default_ctx(binary.device).edt(binary, conn, out)
+
+
+def last_stats(device=0) -> dict:
+    """Counters of the last call on the default context of `device`."""
+    torch = _torch()
+    return _default_ctx(torch.device("cuda", device) if isinstance(device, int) else device).stats()

@@ -1,0 +1,76 @@
+"""ctypes declarations for the C ABI in include/iwpp.h (libiwpp.so)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libiwpp.so")
+
+IWPP_OK = 0
+IWPP_EINVAL = -1
+IWPP_ENOMEM = -2
+IWPP_EDEVICE = -3
+IWPP_EBUSY = -4
+
+# Every symbol include/iwpp.h declares (checked by the CPU tests).
+EXPORTED = (
+    "iwpp_version", "iwpp_create", "iwpp_destroy", "iwpp_last_error",
+    "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats",
+)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("mr_list_capacity", ctypes.c_int64),
+        ("mr_max_sweeps", ctypes.c_int32),
+        ("persistent_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("op", ctypes.c_int32),
+        ("seeds", ctypes.c_int64),
+        ("items", ctypes.c_int64),
+        ("sweeps", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("updates", ctypes.c_int64),
+        ("overflow_restarts", ctypes.c_int64),
+        ("reserved", ctypes.c_int64 * 6),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libiwpp.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1209_3314_amd.build` "
+            "(the GPU library has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    lib.iwpp_version.argtypes = []
+    lib.iwpp_version.restype = i32
+    lib.iwpp_create.argtypes = [i32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.iwpp_create.restype = i32
+    lib.iwpp_destroy.argtypes = [vp]
+    lib.iwpp_destroy.restype = None
+    lib.iwpp_last_error.argtypes = [vp]
+    lib.iwpp_last_error.restype = ctypes.c_char_p
+    lib.iwpp_morph_recon_u8.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
+    lib.iwpp_morph_recon_u8.restype = i32
+    lib.iwpp_edt.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
+    lib.iwpp_edt.restype = i32
+    lib.iwpp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.iwpp_get_stats.restype = i32
+    _lib = lib
+    return lib

@@ -1,0 +1,194 @@
+// Device-side building blocks shared by the reconstruction and distance
+// transform kernels (gfx950, wave64).
+//
+// Cross-workgroup coherence.  On MI355X every XCD has its own L2 and the L2s
+// are not coherent with each other while a kernel runs, so plain loads can
+// return stale lines for data another XCD wrote during the same launch.  The
+// persistent kernels therefore move all data that other workgroups of the same
+// launch read or write with device-scope ("sc1") loads and stores, and publish
+// it by draining the store counter (s_waitcnt vmcnt(0)) before the atomic
+// that makes it reachable.  The alternative -- agent-scope acquire/release,
+// which writes back and invalidates the whole L2 -- costs roughly ten times
+// more per handoff.  Kernel boundaries are coherence points, so data written
+// by an earlier kernel may be read with plain loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace iwpp {
+
+constexpr int kWave = 64;
+constexpr int kSc1 = 16;  // buffer-instruction cache policy bit: device scope
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+// Wait until every store/atomic this wave issued has completed.
+__device__ __forceinline__ void drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// ---- device-coherent scalar accesses (one element per lane) -----------------
+template <typename T>
+__device__ __forceinline__ T cload(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void cstore(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T atomic_add(T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T atomic_or(T* p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T atomic_min(T* p, T v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T atomic_max(T* p, T v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- wave helpers -------------------------------------------------------------
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int mbcnt(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+// lane i receives v from lane i-1; lane 0 receives `fill`.
+__device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+// lane i receives v from lane i+1; lane 63 receives `fill`.
+__device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t fill) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// ---- statistics: sharded counters (8 copies, one per workgroup group) ---------
+// Fields are summed over the shards by the host.
+enum StatField : int {
+  kStatSeeds = 0,
+  kStatItems = 1,
+  kStatSweeps = 2,
+  kStatRounds = 3,
+  kStatUpdates = 4,
+  kStatRestarts = 5,
+  kStatError = 6,
+  kStatFields = 16
+};
+constexpr int kStatShards = 8;
+
+__device__ __forceinline__ void stat_add(unsigned long long* stats, int field, unsigned long long v) {
+  if (v) atomic_add(stats + (blockIdx.x & (kStatShards - 1)) * kStatFields + field, v);
+}
+
+// ---- grid barrier ---------------------------------------------------------------
+// Hierarchical sense-counting barrier for a co-resident (cooperative) grid:
+// workgroups arrive on one of 8 group counters (blockIdx & 7), the last of a
+// group arrives on the top counter, and the last group bumps the generation.
+// Counters sit 256 bytes apart so they do not share a cache line.  Every wait
+// is bounded: on timeout (or when another workgroup raised `abort`) the
+// barrier returns false and the caller must leave the kernel.
+struct GridBarrier {
+  uint32_t group[8][64];
+  uint32_t top[64];
+  uint32_t gen[64];
+  uint32_t abort[64];
+};
+
+constexpr uint32_t kSpinLimit = 1u << 24;  // ~ seconds of polling, far beyond any real wait
+
+__device__ __forceinline__ bool grid_barrier(GridBarrier* b, uint32_t& gen, unsigned long long* stats) {
+  __shared__ uint32_t ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    drain();
+    const uint32_t nwg = gridDim.x;
+    const uint32_t g = blockIdx.x & 7u;
+    const uint32_t in_group = (nwg - g + 7u) >> 3;
+    const uint32_t groups = nwg < 8u ? nwg : 8u;
+    uint32_t res = 1;
+    uint32_t old = atomic_add(&b->group[g][0], 1u);
+    if (old == in_group - 1) {
+      cstore(&b->group[g][0], 0u);
+      drain();
+      uint32_t old2 = atomic_add(&b->top[0], 1u);
+      if (old2 == groups - 1) {
+        cstore(&b->top[0], 0u);
+        drain();
+        cstore(&b->gen[0], gen + 1);
+      }
+    }
+    uint32_t spins = 0;
+    while (cload(&b->gen[0]) == gen) {
+      if (cload(&b->abort[0])) { res = 0; break; }
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kSpinLimit) {
+        cstore(&b->abort[0], 1u);
+        atomic_add(stats + kStatError, 1ull);
+        res = 0;
+        break;
+      }
+    }
+    gen += 1;
+    ok = res;
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// Compiler + memory ordering point for lanes of one wave that exchange data
+// through LDS (LDS instructions of a wave execute in order).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---- per-wave staged append ---------------------------------------------------
+// A wave collects items in an LDS buffer with ballot + mbcnt (no atomics) and
+// flushes it to a global list with one atomic per flush.  `cap_global` bounds
+// the global list; items past it are dropped and *ovf is set.  The fill level
+// `n` is wave-uniform and lives in a register.
+struct WaveStage {
+  uint32_t* items;  // LDS, `cap` entries
+  uint32_t cap;
+  uint32_t n;
+};
+
+__device__ __forceinline__ void stage_flush(WaveStage& s, uint32_t* list, uint32_t* count, uint32_t cap_global,
+                                            uint32_t* ovf) {
+  const uint32_t n = s.n;
+  if (n == 0) return;
+  wave_sync();
+  uint32_t base = 0;
+  if (lane() == 0) base = atomic_add(count, n);
+  base = readlane(base, 0);
+  for (uint32_t i = lane(); i < n; i += kWave) {
+    uint32_t slot = base + i;
+    if (slot < cap_global) cstore(list + slot, s.items[i]);
+  }
+  if (base + n > cap_global && lane() == 0) cstore(ovf, 1u);
+  wave_sync();
+  s.n = 0;
+}
+
+// Append `item` for every lane with `pred`; flushes first if the stage could overflow.
+__device__ __forceinline__ void stage_append(WaveStage& s, bool pred, uint32_t item, uint32_t* list,
+                                             uint32_t* count, uint32_t cap_global, uint32_t* ovf) {
+  const uint64_t m = ballot(pred);
+  if (m == 0) return;
+  const uint32_t k = (uint32_t)__popcll(m);
+  if (s.n + k > s.cap) stage_flush(s, list, count, cap_global, ovf);
+  if (pred) s.items[s.n + mbcnt(m)] = item;
+  s.n += k;
+}
+
+}  // namespace iwpp

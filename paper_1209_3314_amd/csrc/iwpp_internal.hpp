@@ -1,0 +1,64 @@
+// Internal declarations shared by the host library and the kernel sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace iwpp {
+
+struct GridBarrier;
+
+// Reconstruction launch arguments (device pointers, scratch owned by the context).
+struct MrArgs {
+  const uint8_t* marker;
+  const uint8_t* mask;
+  uint8_t* out;
+  int32_t h, w;
+  int32_t tiles_y, tiles_x;
+  uint32_t ntiles;
+  uint32_t list_cap;     // capacity of each round's tile list (<= ntiles)
+  int32_t max_sweeps;    // sweep iterations per propagation visit before re-listing
+  int32_t seed_sweeps;   // sweep iterations per tile in the seed pass
+  uint32_t* flags;       // [2][ntiles] "already listed" per round parity
+  uint32_t* lists;       // [2][ntiles] tile lists per round parity
+  uint32_t* counts;      // [3][64] list fill levels, one per round mod 3 (256 B apart)
+  uint32_t* lost;        // [2][64] a listed tile was dropped (capacity), per parity
+  GridBarrier* bar;
+  unsigned long long* stats;  // [8 shards][16 fields]
+};
+
+// Distance-transform launch arguments.
+struct EdtArgs {
+  const uint8_t* bin;
+  int32_t* sqdist;
+  int32_t* nearest;
+  int32_t h, w;
+  uint32_t npix;
+  unsigned long long* key0;  // [npix] packed (d2 << 32 | y << 16 | x), ~0 = none
+  unsigned long long* key1;  // [npix]
+  uint32_t* stamp;           // [npix] last round that listed the pixel
+  uint32_t* lists;           // [2][npix] frontier, packed (y << 16 | x)
+  uint32_t* counts;          // [3][64]
+  uint32_t* ovf;             // [64] never set: a frontier holds each pixel once
+  GridBarrier* bar;
+  unsigned long long* stats;
+};
+
+// Bytes of the scratch areas the kernels expect.
+constexpr size_t kBarrierBytes = 4096;
+constexpr size_t kCountsBytes = 3 * 64 * 4;
+constexpr size_t kLostBytes = 2 * 64 * 4;
+constexpr size_t kStatsBytes = 8 * 16 * 8;
+
+int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, const char** err);
+int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, const char** err);
+int zero_words(uint32_t* p, size_t nwords, hipStream_t stream);
+
+// Workgroups for a cooperative (persistent) launch of `fn`: every one must be
+// resident at once, since they meet at grid barriers.  The runtime's occupancy
+// figure is capped by a 128 KiB LDS budget per CU and by 4 workgroups per CU;
+// grids sized from the raw figure (8 per CU for a 16 KiB kernel) were measured
+// not to be co-resident on MI355X, while these caps are.
+uint32_t persistent_grid(const void* fn, int per_cu, int cus);
+
+}  // namespace iwpp

@@ -1,0 +1,130 @@
+"""Reconstruction on the GPU, through the C ABI, against the oracle: bit-exact
+on every case (the result is unique, Sec. 2.1)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_3314_amd import synth
+from tests.gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch, iw = require_gpu()
+    ctx = iw.Context(0)
+    yield torch, iw, ctx
+    ctx.close()
+
+
+def run(env, J, I, conn, ctx=None, out=None):
+    torch, iw, c = env
+    c = ctx or c
+    d = torch.device("cuda", 0)
+    Jd, Id = torch.from_numpy(J).to(d), torch.from_numpy(I).to(d)
+    r = c.morph_recon(Jd, Id, conn, out=out)
+    torch.cuda.synchronize()
+    st = c.stats()
+    assert st["status"] == 0, st
+    return r.cpu().numpy(), st
+
+
+SHAPES = [(1, 1), (1, 200), (200, 1), (2, 3), (63, 65), (64, 64), (65, 129), (130, 257), (300, 500), (129, 64)]
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_images(env, shape, conn):
+    h, w = shape
+    rng = np.random.default_rng(h * 1000 + w + conn)
+    for levels in (4, 256):
+        I = rng.integers(0, levels, (h, w)).astype(np.uint8)
+        J = (I * rng.random((h, w)) ** 3).astype(np.uint8)
+        announce("mr random", h, w, conn, levels)
+        g, _ = run(env, J, I, conn)
+        assert np.array_equal(g, oracle.mr_fh(J, I, conn))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_generator_images(env, conn):
+    for h, w, seed in [(200, 300, 1), (517, 389, 2), (1000, 70, 3)]:
+        J, I = synth.mr_inputs(h, w, seed, n_disks=max(1, h * w // 6000), radius=(5, 20), offset=32)
+        announce("mr synth", h, w, conn)
+        g, _ = run(env, J, I, conn)
+        assert np.array_equal(g, oracle.mr_fh(J, I, conn))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_small_workload(env, conn):
+    J, I = synth.workload_mr_small()
+    announce("mr 512x512", conn)
+    g, st = run(env, J, I, conn)
+    assert np.array_equal(g, oracle.mr_fh(J, I, conn))
+
+
+def test_marker_above_mask_and_in_place(env):
+    torch, iw, ctx = env
+    rng = np.random.default_rng(7)
+    I = rng.integers(0, 256, (150, 170)).astype(np.uint8)
+    J = rng.integers(0, 256, (150, 170)).astype(np.uint8)  # often above the mask
+    expect = oracle.mr_fh(J, I, 8)
+    announce("mr clamp")
+    g, _ = run(env, J, I, 8)
+    assert np.array_equal(g, expect)
+    d = torch.device("cuda", 0)
+    Jd, Id = torch.from_numpy(J).to(d), torch.from_numpy(I).to(d)
+    announce("mr in place")
+    r = ctx.morph_recon(Jd, Id, 8, out=Jd)
+    torch.cuda.synchronize()
+    assert r.data_ptr() == Jd.data_ptr() and np.array_equal(Jd.cpu().numpy(), expect)
+
+
+@pytest.mark.parametrize("cap", [1, 2, 5])
+def test_forced_overflow_restarts(env, cap):
+    """A work list too small for the round drops tiles and forces dense re-seeds;
+    the result must not change (Sec. 3.2: re-running from a partial output
+    gives the same solution)."""
+    torch, iw, _ = env
+    J, I = synth.mr_inputs(320, 448, 5, n_disks=6, radius=(5, 20), offset=32)
+    ctx = iw.Context(0, mr_list_capacity=cap)
+    try:
+        announce("mr overflow cap", cap)
+        g, st = run(env, J, I, 8, ctx=ctx)
+    finally:
+        ctx.close()
+    assert np.array_equal(g, oracle.mr_fh(J, I, 8))
+    assert st["overflow_restarts"] >= 1
+
+
+@pytest.mark.parametrize("opts", [dict(persistent_blocks=1), dict(persistent_blocks=7), dict(mr_max_sweeps=1),
+                                  dict(mr_max_sweeps=3, persistent_blocks=64)])
+def test_tunings_do_not_change_bytes(env, opts):
+    torch, iw, _ = env
+    J, I = synth.mr_inputs(400, 333, 9, n_disks=10, radius=(5, 20), offset=40)
+    ctx = iw.Context(0, **opts)
+    try:
+        announce("mr tuning", opts)
+        g, _ = run(env, J, I, 4, ctx=ctx)
+    finally:
+        ctx.close()
+    assert np.array_equal(g, oracle.mr_fh(J, I, 4))
+
+
+def test_repeatable(env):
+    J, I = synth.mr_inputs(700, 900, 13, n_disks=20, radius=(5, 20), offset=32)
+    announce("mr repeat")
+    first, _ = run(env, J, I, 8)
+    for _ in range(5):
+        g, _ = run(env, J, I, 8)
+        assert np.array_equal(g, first)
+    assert np.array_equal(first, oracle.mr_fh(J, I, 8))
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_whole_slide_tile_16k(env, conn):
+    """The 16384^2 workload in the benchmark's configuration, every pixel."""
+    J, I = synth.workload_mr_16k()
+    announce("mr 16384^2 conn", conn)
+    g, st = run(env, J, I, conn)
+    assert np.array_equal(g, oracle.mr_fh(J, I, conn))
