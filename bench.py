@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the IWPP hot path on one MI355X.
+
+One step = the whole path over one batch of synthetic input, inputs already
+resident in HBM:
+  * grayscale reconstruction by dilation of the 16384 x 16384 whole-slide-tile
+    workload, 8-connected and 4-connected (seed pass, seed detection,
+    persistent propagation);
+  * propagation EDT of the 4096 x 4096 nucleus-like workload, 8-connected
+    (initialisation, rounds, finalisation).
+`value` is pixels processed per second over the timed steps (Mpixel/s).
+
+The roofline object describes the kernel that takes the most time per step:
+its algorithmic bytes per launch (the paper's work model, with the oracle's
+work counts) divided by its average launch time from HIP events recorded
+around each launch on the benchmark's stream.  `traffic` is the measured HBM
+traffic of that kernel from the committed rocprofv3 counter summary when it
+was taken on the current kernel sources, else null.
+
+The CPU baseline runs the oracle (single-threaded C) over one full step and
+doubles as the bit-exactness check of the GPU outputs.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s morph-recon & EDT (bit-exact) + batched p50/p99 tile latency vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_1209_3314_amd", "csrc")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(part: str, kernel: str, n: int, q_ref: int, conn: int) -> float:
+    """Bytes the method itself moves, attributed to the kernel that does that
+    part of the work.  Reconstruction: the raster and anti-raster passes read I
+    and J and write J (6 B/px, done by the seed pass) and every queue item moves
+    10 + 2*conn bytes (done by propagation; detection is folded into the
+    anti-raster pass in Algorithm 2 and gets no bytes).  EDT: initialisation
+    reads the input and writes the state (5 B/px); the rounds move 24 + 4*conn
+    bytes per frontier item and the finalisation reads the state and writes two
+    int32 maps (12 B/px)."""
+    if part.startswith("mr"):
+        if kernel == "mr_seed":
+            return 6.0 * n
+        if kernel == "mr_propagate":
+            return float(10 + 2 * conn) * q_ref
+        return 0.0
+    if kernel == "edt_init":
+        return 5.0 * n
+    if kernel == "edt_rounds":
+        return 12.0 * n + float(24 + 4 * conn) * q_ref
+    return 0.0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle run (then no bit-exactness check and no work counts)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (reference for rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        a = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 1 << 30, "bytes_written_per_launch": 1 << 30,
+                          "launches": 3}), flush=True)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent tiles would shard one per GPU; see DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1209_3314_amd as iw
+    from paper_1209_3314_amd import synth
+
+    dev = torch.device("cuda", 0)
+    t = time.time()
+    Jm, Im = synth.workload_mr_16k()
+    Be = synth.workload_edt_4k()
+    log(f"generated inputs in {time.time() - t:.1f}s")
+    n_mr, n_edt = Jm.size, Be.size
+    Jd, Id, Bd = torch.from_numpy(Jm).to(dev), torch.from_numpy(Im).to(dev), torch.from_numpy(Be).to(dev)
+    o8, o4 = torch.empty_like(Id), torch.empty_like(Id)
+    sq = torch.empty(Be.shape, dtype=torch.int32, device=dev)
+    nr = torch.empty(Be.shape, dtype=torch.int32, device=dev)
+    ctx = iw.Context(0, profile=True)
+    parts = [("mr16k_conn8", 8), ("mr16k_conn4", 4), ("edt4k_conn8", 8)]
+
+    def step():
+        ctx.morph_recon(Jd, Id, 8, out=o8)
+        ctx.morph_recon(Jd, Id, 4, out=o4)
+        ctx.edt(Bd, 8, out=(sq, nr))
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    gpu_stats = {}
+    for name, conn in parts:  # counters of one call each (not timed)
+        if name.startswith("mr"):
+            ctx.morph_recon(Jd, Id, conn, out=o8 if conn == 8 else o4)
+        else:
+            ctx.edt(Bd, conn, out=(sq, nr))
+        gpu_stats[name] = ctx.stats()
+        assert gpu_stats[name]["status"] == 0, gpu_stats[name]
+    ctx.profile_read()  # drop the warm-up records
+
+    # ---- timed region ----
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - w0) * 1e3
+    dev_ms = e0.elapsed_time(e1)
+    ms_per_step = dev_ms / args.steps
+    records = ctx.profile_read()
+
+    # Per-kernel averages, by part of the step (launch order within a step).
+    per_call = []
+    for name, conn in parts:
+        names = ["reset", "mr_seed", "mr_detect", "mr_propagate"] if name.startswith("mr") else ["reset", "edt_init", "edt_rounds"]
+        per_call.append((name, conn, names))
+    launches_per_step = sum(len(c[2]) for c in per_call)
+    assert len(records) == launches_per_step * args.steps, (len(records), launches_per_step)
+    kern_ms = {}
+    i = 0
+    for _ in range(args.steps):
+        for name, conn, names in per_call:
+            for kn in names:
+                rk, ms = records[i]
+                assert rk == kn, (rk, kn)
+                kern_ms.setdefault((name, kn), []).append(ms)
+                i += 1
+    kernels = {f"{p}/{k}": sum(v) / len(v) for (p, k), v in kern_ms.items()}
+
+    # ---- oracle: CPU baseline + bit-exactness + work counts ----
+    q_ref, cpu = {}, None
+    bit_exact = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        g8, g4 = o8.cpu().numpy(), o4.cpu().numpy()
+        gs, gn = sq.cpu().numpy(), nr.cpu().numpy()
+        t = time.perf_counter()
+        r8, s8 = oracle.mr_fh(Jm, Im, 8, return_stats=True)
+        r4, s4 = oracle.mr_fh(Jm, Im, 4, return_stats=True)
+        es, en, se = oracle.edt_rounds(Be, 8, return_stats=True)
+        cpu_s = time.perf_counter() - t
+        bit_exact = bool(np.array_equal(g8, r8) and np.array_equal(g4, r4) and np.array_equal(gs, es)
+                         and np.array_equal(gn, en))
+        q_ref = {"mr16k_conn8": s8["pops"], "mr16k_conn4": s4["pops"], "edt4k_conn8": se["items"]}
+        cpu = {"value": round((2 * n_mr + n_edt) / cpu_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+               "sample": "one full step (16384^2 reconstruction conn 8 and conn 4, 4096^2 EDT conn 8), "
+                         f"{cpu_s:.1f} s single-threaded C on the host"}
+        log(f"oracle step {cpu_s:.1f}s bit_exact={bit_exact} q_ref={q_ref}")
+
+    # ---- roofline of the dominant kernel ----
+    dom_key = max(kernels, key=kernels.get)
+    dom_part, dom_kernel = dom_key.split("/")
+    dom_conn = dict(parts)[dom_part]
+    dom_n = n_edt if dom_part.startswith("edt") else n_mr
+    roofline = None
+    op_roofline = {}
+    if q_ref:
+        ab = algorithmic_bytes(dom_part, dom_kernel, dom_n, q_ref[dom_part], dom_conn)
+        achieved = ab / (kernels[dom_key] * 1e-3) / 1e9
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            with open(TRAFFIC_FILE) as f:
+                tr = json.load(f)
+            ent = tr.get("kernels", {}).get(dom_key)
+            if ent and tr.get("kernel_source_sha") == kernel_source_sha():
+                traffic = ent["hbm_bytes_per_launch"]
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_key,
+                    "algorithmic_bytes": ab, "avg_ms": round(kernels[dom_key], 4)}
+        for name, conn in parts:
+            n = n_edt if name.startswith("edt") else n_mr
+            ks = [k for k in kernels if k.startswith(name + "/")]
+            ms = sum(kernels[k] for k in ks)
+            b = sum(algorithmic_bytes(name, k.split("/")[1], n, q_ref[name], conn) for k in ks)
+            op_roofline[name] = {"ms": round(ms, 4), "algorithmic_GB": round(b / 1e9, 4),
+                                 "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "mpix_s": round(n / (ms * 1e-3) / 1e6, 1)}
+
+    px = 2 * n_mr + n_edt
+    value = px / (ms_per_step * 1e-3) / 1e6
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8/int32", "data": "synthetic",
+        "config": {"workload": "morph-recon 16384x16384 uint8 conn 8 + conn 4 (20k disks r5-30, offset 48, seed 0) "
+                               "+ EDT 4096x4096 conn 8 (30% nucleus-like features, seed 0)",
+                   "pixels_per_step": px},
+        "bit_exact": bit_exact, "roofline": roofline, "cpu_baseline": cpu,
+        "per_op": op_roofline, "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
+        "wall_ms_per_step": round(wall_ms / args.steps, 4),
+        "work": {"q_ref": q_ref, "gpu": gpu_stats},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,7 +64,11 @@ typedef struct {
   int32_t mr_max_sweeps;
   /* Workgroups of the persistent kernels (0 = fill the device). */
   int32_t persistent_blocks;
-  int32_t reserved[8];
+  /* Nonzero: record a HIP event pair around every kernel launch so that
+   * iwpp_profile_read can report per-kernel device times.  Costs two event
+   * records per launch. */
+  int32_t profile;
+  int32_t reserved[7];
 } iwpp_options;
 
 /* Counters of the last compute call on a context (see iwpp_get_stats). */
@@ -80,6 +84,21 @@ typedef struct {
   int64_t overflow_restarts; /* MR: dense re-seeds after a work-list overflow */
   int64_t reserved[6];
 } iwpp_stats;
+
+/* One timed kernel launch (see iwpp_options.profile). */
+typedef struct {
+  int32_t kernel; /* IWPP_K_* */
+  float ms;       /* device time between the events around the launch */
+} iwpp_kernel_time;
+
+enum {
+  IWPP_K_RESET = 0,        /* counter reset at the start of every call */
+  IWPP_K_MR_SEED = 1,      /* reconstruction seed pass (tile sweeps) */
+  IWPP_K_MR_DETECT = 2,    /* reconstruction seed detection */
+  IWPP_K_MR_PROPAGATE = 3, /* reconstruction persistent propagation */
+  IWPP_K_EDT_INIT = 4,     /* distance transform initialisation */
+  IWPP_K_EDT_ROUNDS = 5    /* distance transform rounds + finalisation */
+};
 
 /* Library version, (major << 16) | minor. */
 int32_t iwpp_version(void);
@@ -141,6 +160,14 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
  * aliasing each other or the input), IWPP_ENOMEM, IWPP_EDEVICE. */
 int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
                  int32_t width, int32_t conn, void* stream);
+
+/* Per-kernel device times recorded since the previous read (needs
+ * iwpp_options.profile).  Synchronises with every stream the recorded
+ * launches used, writes up to `max` entries in launch order to out[], sets
+ * *n to the number written and clears the record.  Launches beyond the
+ * record's capacity (4096) are not recorded.
+ * Errors: IWPP_EINVAL (NULL arguments), IWPP_EDEVICE. */
+int32_t iwpp_profile_read(iwpp_ctx* ctx, iwpp_kernel_time* out, int32_t max, int32_t* n);
 
 /* Copy the counters of the last compute call into *out.  Synchronises with
  * the stream of that call first.  Errors: IWPP_EINVAL (NULL), IWPP_EDEVICE. */

@@ -55,12 +55,13 @@ class Context:
     context per device and the current torch stream."""
 
     def __init__(self, device: int = 0, mr_list_capacity: int = 0, mr_max_sweeps: int = 0,
-                 persistent_blocks: int = 0):
+                 persistent_blocks: int = 0, profile: bool = False):
         lib = _lib.load()
         opt = _lib.Options()
         opt.mr_list_capacity = int(mr_list_capacity)
         opt.mr_max_sweeps = int(mr_max_sweeps)
         opt.persistent_blocks = int(persistent_blocks)
+        opt.profile = 1 if profile else 0
         h = ctypes.c_void_p()
         rc = lib.iwpp_create(int(device), ctypes.byref(opt), ctypes.byref(h))
         if rc != _lib.IWPP_OK:
@@ -125,6 +126,16 @@ class Context:
         if rc != _lib.IWPP_OK:
             self._err(rc)
         return sq, nr
+
+    def profile_read(self) -> list:
+        """(kernel name, device ms) for every launch since the last read, in
+        launch order (needs ``profile=True``); synchronises."""
+        buf = (_lib.KernelTime * 4096)()
+        n = ctypes.c_int32()
+        rc = self._lib.iwpp_profile_read(self._h, buf, 4096, ctypes.byref(n))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return [(_lib.KERNEL_NAMES.get(buf[i].kernel, str(buf[i].kernel)), float(buf[i].ms)) for i in range(n.value)]
 
     def stats(self) -> dict:
         st = _lib.Stats()

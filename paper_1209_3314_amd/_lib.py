@@ -16,8 +16,10 @@ IWPP_EBUSY = -4
 # Every symbol include/iwpp.h declares (checked by the CPU tests).
 EXPORTED = (
     "iwpp_version", "iwpp_create", "iwpp_destroy", "iwpp_last_error",
-    "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats",
+    "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats", "iwpp_profile_read",
 )
+
+KERNEL_NAMES = {0: "reset", 1: "mr_seed", 2: "mr_detect", 3: "mr_propagate", 4: "edt_init", 5: "edt_rounds"}
 
 
 class Options(ctypes.Structure):
@@ -25,8 +27,13 @@ class Options(ctypes.Structure):
         ("mr_list_capacity", ctypes.c_int64),
         ("mr_max_sweeps", ctypes.c_int32),
         ("persistent_blocks", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -72,5 +79,7 @@ def load():
     lib.iwpp_edt.restype = i32
     lib.iwpp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.iwpp_get_stats.restype = i32
+    lib.iwpp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+    lib.iwpp_profile_read.restype = i32
     _lib = lib
     return lib

@@ -24,7 +24,59 @@ struct iwpp_ctx {
   hipStream_t last_stream = nullptr;
   int last_op = 0;
   bool have_call = false;
+  iwpp::Recorder rec;
 };
+
+namespace iwpp {
+
+void Recorder::begin(int kernel, hipStream_t s) {
+  open_ = false;
+  if (!enabled || count_ >= kCap) return;
+  if (count_ >= created_) {
+    if (hipEventCreate(&start_[count_]) != hipSuccess) return;
+    if (hipEventCreate(&stop_[count_]) != hipSuccess) {
+      (void)hipEventDestroy(start_[count_]);
+      return;
+    }
+    created_ = count_ + 1;
+  }
+  if (hipEventRecord(start_[count_], s) != hipSuccess) return;
+  kernel_[count_] = kernel;
+  open_ = true;
+}
+
+void Recorder::end(hipStream_t s) {
+  if (!open_) return;
+  open_ = false;
+  if (hipEventRecord(stop_[count_], s) == hipSuccess) count_++;
+}
+
+int Recorder::read(int* kernels, float* ms, int max) {
+  int n = 0;
+  for (int i = 0; i < count_ && n < max; ++i) {
+    float t = 0.f;
+    if (hipEventSynchronize(stop_[i]) != hipSuccess || hipEventElapsedTime(&t, start_[i], stop_[i]) != hipSuccess) {
+      (void)hipGetLastError();
+      t = -1.f;
+    }
+    kernels[n] = kernel_[i];
+    ms[n] = t;
+    n++;
+  }
+  count_ = 0;
+  return n;
+}
+
+void Recorder::release() {
+  for (int i = 0; i < created_; ++i) {
+    (void)hipEventDestroy(start_[i]);
+    (void)hipEventDestroy(stop_[i]);
+  }
+  created_ = 0;
+  count_ = 0;
+}
+
+}  // namespace iwpp
 
 namespace {
 
@@ -88,8 +140,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Clear counters, list fill levels, flags and the barrier for a new call.
 int32_t reset_fixed(iwpp_ctx* ctx, hipStream_t stream) {
-  if (iwpp::zero_words(reinterpret_cast<uint32_t*>(ctx->fixed), kFixedBytes / 4, stream) != 0)
-    return fail(ctx, IWPP_EDEVICE, "reset kernel launch failed");
+  ctx->rec.begin(IWPP_K_RESET, stream);
+  const int r = iwpp::zero_words(reinterpret_cast<uint32_t*>(ctx->fixed), kFixedBytes / 4, stream);
+  ctx->rec.end(stream);
+  if (r != 0) return fail(ctx, IWPP_EDEVICE, "reset kernel launch failed");
   return IWPP_OK;
 }
 
@@ -118,6 +172,7 @@ int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out) {
   }
   ctx->device = device;
   if (opt) ctx->opt = *opt;
+  ctx->rec.enabled = ctx->opt.profile != 0;
   DeviceGuard g(device);
   void* p = nullptr;
   if (!g.ok || hipMalloc(&p, kFixedBytes) != hipSuccess) {
@@ -142,6 +197,7 @@ void iwpp_destroy(iwpp_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    ctx->rec.release();
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->fixed) (void)hipFree(ctx->fixed);
   }
@@ -193,7 +249,7 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
   a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
   if ((rc = reset_fixed(ctx, st)) != IWPP_OK) return rc;
   const char* e = "";
-  if (iwpp::mr_launch(a, conn, ctx->opt.persistent_blocks, st, &e) != 0) {
+  if (iwpp::mr_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
     (void)hipGetLastError();
     return fail(ctx, IWPP_EDEVICE, std::string("morph_recon: ") + e);
   }
@@ -240,13 +296,30 @@ int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t*
   a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
   if ((rc = reset_fixed(ctx, st)) != IWPP_OK) return rc;
   const char* e = "";
-  if (iwpp::edt_launch(a, conn, ctx->opt.persistent_blocks, st, &e) != 0) {
+  if (iwpp::edt_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
     (void)hipGetLastError();
     return fail(ctx, IWPP_EDEVICE, std::string("edt: ") + e);
   }
   ctx->last_stream = st;
   ctx->last_op = 2;
   ctx->have_call = true;
+  return IWPP_OK;
+}
+
+int32_t iwpp_profile_read(iwpp_ctx* ctx, iwpp_kernel_time* out, int32_t max, int32_t* n) {
+  if (!ctx) return IWPP_EINVAL;
+  if (!out || !n || max < 0) return fail(ctx, IWPP_EINVAL, "profile_read: NULL argument");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, IWPP_EDEVICE, "profile_read: cannot select the context's device");
+  static thread_local int ks[iwpp::Recorder::kCap];
+  static thread_local float ms[iwpp::Recorder::kCap];
+  const int m = ctx->rec.read(ks, ms, iwpp::Recorder::kCap);
+  int w = 0;
+  for (int i = 0; i < m && w < max; ++i, ++w) {
+    out[w].kernel = ks[i];
+    out[w].ms = ms[i];
+  }
+  *n = w;
   return IWPP_OK;
 }
 

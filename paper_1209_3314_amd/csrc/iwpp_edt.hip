@@ -181,14 +181,16 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
 
 }  // namespace edt
 
-int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, const char** err) {
+int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err) {
   using namespace edt;
   uint32_t init_blocks = (a.npix + 255u) / 256u;
   if (init_blocks > 2048u) init_blocks = 2048u;
+  rec->begin(4, stream);
   if (conn == 8)
     hipLaunchKernelGGL(k_init<8>, dim3(init_blocks), dim3(256), 0, stream, a);
   else
     hipLaunchKernelGGL(k_init<4>, dim3(init_blocks), dim3(256), 0, stream, a);
+  rec->end(stream);
   if (hipGetLastError() != hipSuccess) {
     *err = "EDT init launch failed";
     return -1;
@@ -204,7 +206,10 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
   if (persistent_blocks > 0 && (uint32_t)persistent_blocks < blocks) blocks = (uint32_t)persistent_blocks;
   EdtArgs args = a;
   void* kargs[] = {&args};
-  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), kargs, 0, stream) != hipSuccess) {
+  rec->begin(5, stream);
+  const hipError_t le = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), kargs, 0, stream);
+  rec->end(stream);
+  if (le != hipSuccess) {
     *err = "EDT rounds launch failed";
     return -1;
   }

@@ -50,8 +50,29 @@ constexpr size_t kCountsBytes = 3 * 64 * 4;
 constexpr size_t kLostBytes = 2 * 64 * 4;
 constexpr size_t kStatsBytes = 8 * 16 * 8;
 
-int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, const char** err);
-int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, const char** err);
+// Optional per-launch event timing (iwpp_options.profile).  begin/end bracket
+// one kernel launch on `s`; both are no-ops when disabled or full.
+class Recorder {
+ public:
+  static constexpr int kCap = 4096;
+  bool enabled = false;
+  void begin(int kernel, hipStream_t s);
+  void end(hipStream_t s);
+  // Completed records since the last read: returns the count written.
+  int read(int* kernels, float* ms, int max);
+  void release();
+
+ private:
+  hipEvent_t start_[kCap] = {};
+  hipEvent_t stop_[kCap] = {};
+  int kernel_[kCap] = {};
+  int created_ = 0;
+  int count_ = 0;
+  bool open_ = false;
+};
+
+int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err);
+int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err);
 int zero_words(uint32_t* p, size_t nwords, hipStream_t stream);
 
 // Workgroups for a cooperative (persistent) launch of `fn`: every one must be

@@ -562,22 +562,26 @@ __global__ __launch_bounds__(256) void k_propagate(MrArgs a) {
 }  // namespace mr
 
 // ---- host-side launch -----------------------------------------------------------------
-int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, const char** err) {
+int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err) {
   using namespace mr;
   const uint32_t seed_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  rec->begin(1, stream);
   if (conn == 8)
     hipLaunchKernelGGL(k_seed<8>, dim3(seed_blocks), dim3(256), 0, stream, a);
   else
     hipLaunchKernelGGL(k_seed<4>, dim3(seed_blocks), dim3(256), 0, stream, a);
+  rec->end(stream);
   if (hipGetLastError() != hipSuccess) {
     *err = "seed-pass launch failed";
     return -1;
   }
   uint32_t det_blocks = seed_blocks < 2048u ? seed_blocks : 2048u;
+  rec->begin(2, stream);
   if (conn == 8)
     hipLaunchKernelGGL(k_detect<8>, dim3(det_blocks), dim3(256), 0, stream, a);
   else
     hipLaunchKernelGGL(k_detect<4>, dim3(det_blocks), dim3(256), 0, stream, a);
+  rec->end(stream);
   if (hipGetLastError() != hipSuccess) {
     *err = "seed-detect launch failed";
     return -1;
@@ -593,7 +597,10 @@ int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stre
   if (persistent_blocks > 0 && (uint32_t)persistent_blocks < blocks) blocks = (uint32_t)persistent_blocks;
   MrArgs args = a;
   void* kargs[] = {&args};
-  if (hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), kargs, 0, stream) != hipSuccess) {
+  rec->begin(3, stream);
+  const hipError_t le = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), kargs, 0, stream);
+  rec->end(stream);
+  if (le != hipSuccess) {
     *err = "propagation launch failed";
     return -1;
   }
