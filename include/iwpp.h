@@ -74,7 +74,7 @@ typedef struct {
 /* Counters of the last compute call on a context (see iwpp_get_stats). */
 typedef struct {
   int32_t status;            /* IWPP_OK, or IWPP_EDEVICE if a kernel hit a safety limit */
-  int32_t op;                /* 1 = reconstruction, 2 = distance transform */
+  int32_t op;                /* 1 = reconstruction, 2 = distance transform, 3 = batch */
   int64_t seeds;             /* MR: pixels meeting the seed condition of Alg. 5 after the seed pass;
                                 EDT: contour features (initial frontier) */
   int64_t items;             /* MR: tile visits in propagation; EDT: frontier items over all rounds */
@@ -160,6 +160,38 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
  * aliasing each other or the input), IWPP_ENOMEM, IWPP_EDEVICE. */
 int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
                  int32_t width, int32_t conn, void* stream);
+
+/* One image of a batch (see iwpp_run_batch). */
+typedef struct {
+  int32_t op;          /* IWPP_OP_RECON or IWPP_OP_EDT */
+  int32_t conn;        /* 4 or 8 */
+  int32_t height;
+  int32_t width;
+  const uint8_t* in0;  /* recon: marker; EDT: binary (0 = feature) */
+  const uint8_t* in1;  /* recon: mask; EDT: NULL */
+  void* out0;          /* recon: uint8 result (may equal in0); EDT: int32 sqdist */
+  void* out1;          /* recon: NULL; EDT: int32 nearest */
+} iwpp_job;
+
+enum { IWPP_OP_RECON = 1, IWPP_OP_EDT = 2 };
+
+/* Process many images of mixed sizes and both operations with few launches:
+ * jobs are grouped by (op, conn) and every group runs as one seed pass and
+ * one persistent propagation launch over all of its images (reconstruction)
+ * or one initialisation and one persistent round launch (EDT), so small
+ * images share the device instead of each leaving it mostly idle.  Every
+ * result is identical to the corresponding single-image call (each image's
+ * reconstruction is unique; EDT images advance in the same rounds, each by its
+ * own round semantics).
+ *   jobs : host array of n descriptors (copied before the call returns)
+ *   n    : >= 1
+ * Each job obeys the rules of iwpp_morph_recon_u8 / iwpp_edt; in addition no
+ * output may overlap another job's input or output.  A recon group must have
+ * fewer than 2^32 pixels per image; an EDT group fewer than 2^32 pixels in
+ * total.  Counters from iwpp_get_stats cover the whole batch.
+ * Errors: IWPP_EINVAL (bad job: the message names its index), IWPP_ENOMEM,
+ * IWPP_EDEVICE. */
+int32_t iwpp_run_batch(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, void* stream);
 
 /* Per-kernel device times recorded since the previous read (needs
  * iwpp_options.profile).  Synchronises with every stream the recorded

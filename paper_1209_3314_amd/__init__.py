@@ -127,6 +127,46 @@ class Context:
             self._err(rc)
         return sq, nr
 
+    def run_batch(self, jobs: list) -> None:
+        """Run many images in few launches (see iwpp_run_batch).  Each job is a
+        dict: reconstruction ``{"op": "recon", "marker", "mask", "out", "conn"}``
+        or EDT ``{"op": "edt", "binary", "sqdist", "nearest", "conn"}`` with
+        tensors on this context's device (outputs preallocated)."""
+        torch = _torch()
+        if not jobs:
+            raise ValueError("empty batch")
+        arr = (_lib.Job * len(jobs))()
+        dev = None
+        for i, j in enumerate(jobs):
+            conn = int(j.get("conn", 8))
+            if conn not in (4, 8):
+                raise ValueError(f"job {i}: conn must be 4 or 8")
+            if j["op"] == "recon":
+                _check_image(j["mask"], f"job {i} mask", torch.uint8, dev)
+                dev = j["mask"].device
+                _check_image(j["marker"], f"job {i} marker", torch.uint8, dev)
+                _check_image(j["out"], f"job {i} out", torch.uint8, dev)
+                if not (j["marker"].shape == j["mask"].shape == j["out"].shape):
+                    raise ValueError(f"job {i}: shapes differ")
+                h, w = j["mask"].shape
+                arr[i] = _lib.Job(_lib.IWPP_OP_RECON, conn, h, w, j["marker"].data_ptr(), j["mask"].data_ptr(),
+                                  j["out"].data_ptr(), None)
+            elif j["op"] == "edt":
+                _check_image(j["binary"], f"job {i} binary", torch.uint8, dev)
+                dev = j["binary"].device
+                _check_image(j["sqdist"], f"job {i} sqdist", torch.int32, dev)
+                _check_image(j["nearest"], f"job {i} nearest", torch.int32, dev)
+                if not (j["binary"].shape == j["sqdist"].shape == j["nearest"].shape):
+                    raise ValueError(f"job {i}: shapes differ")
+                h, w = j["binary"].shape
+                arr[i] = _lib.Job(_lib.IWPP_OP_EDT, conn, h, w, j["binary"].data_ptr(), None,
+                                  j["sqdist"].data_ptr(), j["nearest"].data_ptr())
+            else:
+                raise ValueError(f"job {i}: op must be 'recon' or 'edt'")
+        rc = self._lib.iwpp_run_batch(self._h, arr, len(jobs), self._stream(dev))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+
     def profile_read(self) -> list:
         """(kernel name, device ms) for every launch since the last read, in
         launch order (needs ``profile=True``); synchronises."""

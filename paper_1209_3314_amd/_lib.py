@@ -16,8 +16,10 @@ IWPP_EBUSY = -4
 # Every symbol include/iwpp.h declares (checked by the CPU tests).
 EXPORTED = (
     "iwpp_version", "iwpp_create", "iwpp_destroy", "iwpp_last_error",
-    "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats", "iwpp_profile_read",
+    "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats", "iwpp_profile_read", "iwpp_run_batch",
 )
+IWPP_OP_RECON = 1
+IWPP_OP_EDT = 2
 
 KERNEL_NAMES = {0: "reset", 1: "mr_seed", 2: "mr_detect", 3: "mr_propagate", 4: "edt_init", 5: "edt_rounds"}
 
@@ -29,6 +31,19 @@ class Options(ctypes.Structure):
         ("persistent_blocks", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("conn", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("width", ctypes.c_int32),
+        ("in0", ctypes.c_void_p),
+        ("in1", ctypes.c_void_p),
+        ("out0", ctypes.c_void_p),
+        ("out1", ctypes.c_void_p),
     ]
 
 
@@ -79,6 +94,8 @@ def load():
     lib.iwpp_edt.restype = i32
     lib.iwpp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.iwpp_get_stats.restype = i32
+    lib.iwpp_run_batch.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
+    lib.iwpp_run_batch.restype = i32
     lib.iwpp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
     lib.iwpp_profile_read.restype = i32
     _lib = lib

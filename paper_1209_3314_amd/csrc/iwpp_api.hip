@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/iwpp.h"
 #include "iwpp_device.hpp"
@@ -138,12 +139,109 @@ int32_t ensure_scratch(iwpp_ctx* ctx, size_t bytes) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Clear counters, list fill levels, flags and the barrier for a new call.
-int32_t reset_fixed(iwpp_ctx* ctx, hipStream_t stream) {
+// Clear list fill levels, lost flags and the barrier before a launch group,
+// and the statistics too at the start of a call.
+int32_t reset_fixed(iwpp_ctx* ctx, hipStream_t stream, bool stats) {
   ctx->rec.begin(IWPP_K_RESET, stream);
-  const int r = iwpp::zero_words(reinterpret_cast<uint32_t*>(ctx->fixed), kFixedBytes / 4, stream);
+  const int r = iwpp::zero_words(reinterpret_cast<uint32_t*>(ctx->fixed), (stats ? kFixedBytes : kOffStats) / 4, stream);
   ctx->rec.end(stream);
   if (r != 0) return fail(ctx, IWPP_EDEVICE, "reset kernel launch failed");
+  return IWPP_OK;
+}
+
+void bind_fixed_mr(iwpp_ctx* ctx, iwpp::MrArgs& a) {
+  a.counts = reinterpret_cast<uint32_t*>(ctx->fixed + kOffCounts);
+  a.lost = reinterpret_cast<uint32_t*>(ctx->fixed + kOffLost);
+  a.bar = reinterpret_cast<iwpp::GridBarrier*>(ctx->fixed + kOffBarrier);
+  a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
+}
+
+void bind_fixed_edt(iwpp_ctx* ctx, iwpp::EdtArgs& a) {
+  a.counts = reinterpret_cast<uint32_t*>(ctx->fixed + kOffCounts);
+  a.ovf = reinterpret_cast<uint32_t*>(ctx->fixed + kOffOvf);
+  a.bar = reinterpret_cast<iwpp::GridBarrier*>(ctx->fixed + kOffBarrier);
+  a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
+}
+
+// Scratch bytes of one reconstruction launch over `ntiles` tiles / `njobs` images.
+size_t mr_scratch_bytes(uint64_t ntiles, uint32_t njobs) {
+  return 5 * align256(ntiles * 4) + align256((size_t)njobs * sizeof(iwpp::MrJob));
+}
+
+// Scratch bytes of one distance-transform launch over `npix` pixels / `njobs` images.
+size_t edt_scratch_bytes(uint64_t npix, uint32_t njobs) {
+  return 4 * align256(npix * 8) + align256(npix * 4) + align256((size_t)njobs * sizeof(iwpp::EdtJob));
+}
+
+// Launch one reconstruction group (jobs already validated; tile_base filled).
+int32_t run_mr(iwpp_ctx* ctx, const std::vector<iwpp::MrJob>& jobs, uint32_t ntiles, int conn, hipStream_t st,
+               bool first) {
+  iwpp::MrArgs a{};
+  const uint32_t nj = (uint32_t)jobs.size();
+  a.job0 = jobs[0];
+  a.njobs = nj;
+  a.ntiles = ntiles;
+  const int64_t cap = ctx->opt.mr_list_capacity;
+  a.list_cap = (cap > 0 && (uint64_t)cap < ntiles) ? (uint32_t)cap : ntiles;
+  a.max_sweeps = ctx->opt.mr_max_sweeps > 0 ? ctx->opt.mr_max_sweeps : 64;
+  a.seed_sweeps = a.max_sweeps;
+  const size_t tb = align256((size_t)ntiles * 4);
+  int32_t rc = ensure_scratch(ctx, mr_scratch_bytes(ntiles, nj));
+  if (rc != IWPP_OK) return rc;
+  // layout: flags[2][T] | lists[2][T] | tile_job[T] | job table
+  a.flags = reinterpret_cast<uint32_t*>(ctx->scratch);
+  a.lists = reinterpret_cast<uint32_t*>(ctx->scratch + 2 * tb);
+  a.tile_job = nullptr;
+  a.jobs = nullptr;
+  if (nj > 1) {
+    iwpp::MrJob* dj = reinterpret_cast<iwpp::MrJob*>(ctx->scratch + 5 * tb);
+    a.tile_job = reinterpret_cast<uint32_t*>(ctx->scratch + 4 * tb);
+    a.jobs = dj;
+    if (hipMemcpyAsync(dj, jobs.data(), nj * sizeof(iwpp::MrJob), hipMemcpyHostToDevice, st) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, IWPP_EDEVICE, "job table upload failed");
+    }
+  }
+  bind_fixed_mr(ctx, a);
+  if ((rc = reset_fixed(ctx, st, first)) != IWPP_OK) return rc;
+  const char* e = "";
+  if (iwpp::mr_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, std::string("morph_recon: ") + e);
+  }
+  return IWPP_OK;
+}
+
+int32_t run_edt(iwpp_ctx* ctx, const std::vector<iwpp::EdtJob>& jobs, uint64_t npix, int conn, hipStream_t st,
+                bool first) {
+  iwpp::EdtArgs a{};
+  const uint32_t nj = (uint32_t)jobs.size();
+  a.job0 = jobs[0];
+  a.njobs = nj;
+  a.npix = (uint32_t)npix;
+  const size_t kb = align256((size_t)npix * 8);
+  int32_t rc = ensure_scratch(ctx, edt_scratch_bytes(npix, nj));
+  if (rc != IWPP_OK) return rc;
+  a.key0 = reinterpret_cast<unsigned long long*>(ctx->scratch);
+  a.key1 = reinterpret_cast<unsigned long long*>(ctx->scratch + kb);
+  a.lists = reinterpret_cast<unsigned long long*>(ctx->scratch + 2 * kb);
+  a.stamp = reinterpret_cast<uint32_t*>(ctx->scratch + 4 * kb);
+  a.jobs = nullptr;
+  if (nj > 1) {
+    iwpp::EdtJob* dj = reinterpret_cast<iwpp::EdtJob*>(ctx->scratch + 4 * kb + align256((size_t)npix * 4));
+    a.jobs = dj;
+    if (hipMemcpyAsync(dj, jobs.data(), nj * sizeof(iwpp::EdtJob), hipMemcpyHostToDevice, st) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, IWPP_EDEVICE, "job table upload failed");
+    }
+  }
+  bind_fixed_edt(ctx, a);
+  if ((rc = reset_fixed(ctx, st, first)) != IWPP_OK) return rc;
+  const char* e = "";
+  if (iwpp::edt_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, std::string("edt: ") + e);
+  }
   return IWPP_OK;
 }
 
@@ -224,35 +322,18 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "morph_recon: cannot select the context's device");
   hipStream_t st = static_cast<hipStream_t>(stream);
 
-  iwpp::MrArgs a{};
-  a.marker = marker;
-  a.mask = mask;
-  a.out = out;
-  a.h = height;
-  a.w = width;
-  a.tiles_y = (height + 63) / 64;
-  a.tiles_x = (width + 63) / 64;
-  a.ntiles = (uint32_t)a.tiles_y * (uint32_t)a.tiles_x;
-  const int64_t cap = ctx->opt.mr_list_capacity;
-  a.list_cap = (cap > 0 && (uint64_t)cap < a.ntiles) ? (uint32_t)cap : a.ntiles;
-  a.max_sweeps = ctx->opt.mr_max_sweeps > 0 ? ctx->opt.mr_max_sweeps : 64;
-  a.seed_sweeps = a.max_sweeps;
-  const size_t flag_bytes = align256((size_t)a.ntiles * 2 * 4);
-  const size_t list_bytes = align256((size_t)a.ntiles * 2 * 4);
-  int32_t rc = ensure_scratch(ctx, flag_bytes + list_bytes);
+  iwpp::MrJob job{};
+  job.marker = marker;
+  job.mask = mask;
+  job.out = out;
+  job.h = height;
+  job.w = width;
+  job.tiles_y = (height + 63) / 64;
+  job.tiles_x = (width + 63) / 64;
+  job.tile_base = 0;
+  const uint32_t ntiles = (uint32_t)job.tiles_y * (uint32_t)job.tiles_x;
+  const int32_t rc = run_mr(ctx, std::vector<iwpp::MrJob>{job}, ntiles, conn, st, true);
   if (rc != IWPP_OK) return rc;
-  a.flags = reinterpret_cast<uint32_t*>(ctx->scratch);
-  a.lists = reinterpret_cast<uint32_t*>(ctx->scratch + flag_bytes);
-  a.counts = reinterpret_cast<uint32_t*>(ctx->fixed + kOffCounts);
-  a.lost = reinterpret_cast<uint32_t*>(ctx->fixed + kOffLost);
-  a.bar = reinterpret_cast<iwpp::GridBarrier*>(ctx->fixed + kOffBarrier);
-  a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
-  if ((rc = reset_fixed(ctx, st)) != IWPP_OK) return rc;
-  const char* e = "";
-  if (iwpp::mr_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, std::string("morph_recon: ") + e);
-  }
   ctx->last_stream = st;
   ctx->last_op = 1;
   ctx->have_call = true;
@@ -274,34 +355,111 @@ int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t*
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "edt: cannot select the context's device");
   hipStream_t st = static_cast<hipStream_t>(stream);
 
-  iwpp::EdtArgs a{};
-  a.bin = binary;
-  a.sqdist = sqdist;
-  a.nearest = nearest;
-  a.h = height;
-  a.w = width;
-  a.npix = (uint32_t)npix;
-  const size_t key_bytes = align256((size_t)npix * 8);
-  const size_t stamp_bytes = align256((size_t)npix * 4);
-  const size_t list_bytes = align256((size_t)npix * 2 * 4);
-  int32_t rc = ensure_scratch(ctx, 2 * key_bytes + stamp_bytes + list_bytes);
+  iwpp::EdtJob job{};
+  job.bin = binary;
+  job.sqdist = sqdist;
+  job.nearest = nearest;
+  job.h = height;
+  job.w = width;
+  job.pix_base = 0;
+  const int32_t rc = run_edt(ctx, std::vector<iwpp::EdtJob>{job}, npix, conn, st, true);
   if (rc != IWPP_OK) return rc;
-  a.key0 = reinterpret_cast<unsigned long long*>(ctx->scratch);
-  a.key1 = reinterpret_cast<unsigned long long*>(ctx->scratch + key_bytes);
-  a.stamp = reinterpret_cast<uint32_t*>(ctx->scratch + 2 * key_bytes);
-  a.lists = reinterpret_cast<uint32_t*>(ctx->scratch + 2 * key_bytes + stamp_bytes);
-  a.counts = reinterpret_cast<uint32_t*>(ctx->fixed + kOffCounts);
-  a.ovf = reinterpret_cast<uint32_t*>(ctx->fixed + kOffOvf);
-  a.bar = reinterpret_cast<iwpp::GridBarrier*>(ctx->fixed + kOffBarrier);
-  a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
-  if ((rc = reset_fixed(ctx, st)) != IWPP_OK) return rc;
-  const char* e = "";
-  if (iwpp::edt_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, std::string("edt: ") + e);
-  }
   ctx->last_stream = st;
   ctx->last_op = 2;
+  ctx->have_call = true;
+  return IWPP_OK;
+}
+
+int32_t iwpp_run_batch(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, void* stream) {
+  if (!ctx) return IWPP_EINVAL;
+  if (!jobs || n < 1) return fail(ctx, IWPP_EINVAL, "run_batch: need at least one job");
+  struct Span {
+    const void* p;
+    size_t n;
+    int job;
+    bool out;
+  };
+  std::vector<Span> spans;
+  for (int32_t i = 0; i < n; ++i) {
+    const iwpp_job& j = jobs[i];
+    const std::string at = "run_batch: job " + std::to_string(i) + ": ";
+    if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_EDT) return fail(ctx, IWPP_EINVAL, at + "op must be RECON or EDT");
+    if (j.conn != 4 && j.conn != 8) return fail(ctx, IWPP_EINVAL, at + "conn must be 4 or 8");
+    if (j.height < 1 || j.width < 1) return fail(ctx, IWPP_EINVAL, at + "height and width must be >= 1");
+    const uint64_t np = (uint64_t)j.height * (uint64_t)j.width;
+    if (j.op == IWPP_OP_RECON) {
+      if (!j.in0 || !j.in1 || !j.out0 || j.out1) return fail(ctx, IWPP_EINVAL, at + "recon needs in0, in1, out0 and no out1");
+      if (np > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, at + "image larger than 2^32 - 1 pixels");
+      spans.push_back({j.in1, np, i, false});
+      if (j.out0 != j.in0) spans.push_back({j.in0, np, i, false});
+      spans.push_back({j.out0, np, i, true});
+    } else {
+      if (!j.in0 || j.in1 || !j.out0 || !j.out1) return fail(ctx, IWPP_EINVAL, at + "EDT needs in0, out0, out1 and no in1");
+      if (j.height > 32767 || j.width > 32767) return fail(ctx, IWPP_EINVAL, at + "EDT sides must be <= 32767");
+      spans.push_back({j.in0, np, i, false});
+      spans.push_back({j.out0, np * 4, i, true});
+      spans.push_back({j.out1, np * 4, i, true});
+    }
+  }
+  for (size_t a = 0; a < spans.size(); ++a)
+    for (size_t b = a + 1; b < spans.size(); ++b)
+      if ((spans[a].out || spans[b].out) && overlaps(spans[a].p, spans[a].n, spans[b].p, spans[b].n))
+        return fail(ctx, IWPP_EINVAL, "run_batch: an output of job " + std::to_string(spans[a].out ? spans[a].job : spans[b].job) +
+                                          " overlaps a buffer of job " + std::to_string(spans[a].out ? spans[b].job : spans[a].job));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, IWPP_EDEVICE, "run_batch: cannot select the context's device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  bool first = true;
+  for (int op : {IWPP_OP_RECON, IWPP_OP_EDT}) {
+    for (int conn : {8, 4}) {
+      if (op == IWPP_OP_RECON) {
+        std::vector<iwpp::MrJob> group;
+        uint64_t tiles = 0;
+        for (int32_t i = 0; i < n; ++i) {
+          const iwpp_job& j = jobs[i];
+          if (j.op != op || j.conn != conn) continue;
+          iwpp::MrJob m{};
+          m.marker = j.in0;
+          m.mask = j.in1;
+          m.out = static_cast<uint8_t*>(j.out0);
+          m.h = j.height;
+          m.w = j.width;
+          m.tiles_y = (j.height + 63) / 64;
+          m.tiles_x = (j.width + 63) / 64;
+          m.tile_base = (uint32_t)tiles;
+          tiles += (uint64_t)m.tiles_y * (uint64_t)m.tiles_x;
+          group.push_back(m);
+        }
+        if (group.empty()) continue;
+        if (tiles >= 0x7FFFFFFFull) return fail(ctx, IWPP_EINVAL, "run_batch: too many reconstruction tiles");
+        const int32_t rc = run_mr(ctx, group, (uint32_t)tiles, conn, st, first);
+        if (rc != IWPP_OK) return rc;
+      } else {
+        std::vector<iwpp::EdtJob> group;
+        uint64_t pix = 0;
+        for (int32_t i = 0; i < n; ++i) {
+          const iwpp_job& j = jobs[i];
+          if (j.op != op || j.conn != conn) continue;
+          iwpp::EdtJob e{};
+          e.bin = j.in0;
+          e.sqdist = static_cast<int32_t*>(j.out0);
+          e.nearest = static_cast<int32_t*>(j.out1);
+          e.h = j.height;
+          e.w = j.width;
+          e.pix_base = (uint32_t)pix;
+          pix += (uint64_t)j.height * (uint64_t)j.width;
+          group.push_back(e);
+          if (pix > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, "run_batch: EDT group larger than 2^32 - 1 pixels");
+        }
+        if (group.empty()) continue;
+        const int32_t rc = run_edt(ctx, group, pix, conn, st, first);
+        if (rc != IWPP_OK) return rc;
+      }
+      first = false;
+    }
+  }
+  ctx->last_stream = st;
+  ctx->last_op = 3;
   ctx->have_call = true;
   return IWPP_OK;
 }

@@ -157,13 +157,16 @@ __device__ __forceinline__ void wave_sync() {
 // flushes it to a global list with one atomic per flush.  `cap_global` bounds
 // the global list; items past it are dropped and *ovf is set.  The fill level
 // `n` is wave-uniform and lives in a register.
-struct WaveStage {
-  uint32_t* items;  // LDS, `cap` entries
+template <typename Item>
+struct WaveStageT {
+  Item* items;  // LDS, `cap` entries
   uint32_t cap;
   uint32_t n;
 };
+using WaveStage = WaveStageT<uint32_t>;
 
-__device__ __forceinline__ void stage_flush(WaveStage& s, uint32_t* list, uint32_t* count, uint32_t cap_global,
+template <typename Item>
+__device__ __forceinline__ void stage_flush(WaveStageT<Item>& s, Item* list, uint32_t* count, uint32_t cap_global,
                                             uint32_t* ovf) {
   const uint32_t n = s.n;
   if (n == 0) return;
@@ -181,8 +184,9 @@ __device__ __forceinline__ void stage_flush(WaveStage& s, uint32_t* list, uint32
 }
 
 // Append `item` for every lane with `pred`; flushes first if the stage could overflow.
-__device__ __forceinline__ void stage_append(WaveStage& s, bool pred, uint32_t item, uint32_t* list,
-                                             uint32_t* count, uint32_t cap_global, uint32_t* ovf) {
+template <typename Item>
+__device__ __forceinline__ void stage_append(WaveStageT<Item>& s, bool pred, Item item, Item* list, uint32_t* count,
+                                             uint32_t cap_global, uint32_t* ovf) {
   const uint64_t m = ballot(pred);
   if (m == 0) return;
   const uint32_t k = (uint32_t)__popcll(m);

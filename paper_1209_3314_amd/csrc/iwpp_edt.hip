@@ -49,45 +49,54 @@ __device__ __forceinline__ void nb_off(int k, int& dy, int& dx) {
   }
 }
 
+__device__ __forceinline__ unsigned long long make_item(uint32_t job, int y, int x) {
+  return ((unsigned long long)job << 32) | pack_yx(y, x);
+}
+
+__device__ __forceinline__ const EdtJob& job_of(const EdtArgs& a, uint32_t j) { return a.njobs == 1u ? a.job0 : a.jobs[j]; }
+
 // Initial state and the first frontier: the contour features (features with a
-// non-feature neighbour, Algorithm 6 initialisation).
+// non-feature neighbour, Algorithm 6 initialisation).  blockIdx.y = image.
 template <int CONN>
 __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ unsigned long long stage_mem[kWavesPerBlock][kStageCap];
   const int w = threadIdx.x / kWave;
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
+  WaveStageT<unsigned long long> s = {stage_mem[w], (uint32_t)kStageCap, 0u};
+  const uint32_t j = blockIdx.y;
+  const EdtJob job = job_of(a, j);
+  const uint32_t npx = (uint32_t)job.h * (uint32_t)job.w;
+  unsigned long long* list1 = a.lists + a.npix;  // the first frontier is read by round 1: list parity 1, count slot 1
   uint32_t contour = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < a.npix; base += stride) {
+  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < npx; base += stride) {
     const uint32_t p = base + (uint32_t)lane();
-    const bool valid = p < a.npix;
+    const bool valid = p < npx;
     bool c = false;
-    uint32_t item = 0;
+    int y = 0, x = 0;
     if (valid) {
-      const int y = (int)(p / (uint32_t)a.w), x = (int)(p - (uint32_t)y * (uint32_t)a.w);
-      item = pack_yx(y, x);
-      const bool feat = a.bin[p] == 0;
-      const unsigned long long k0 = feat ? (unsigned long long)item : kNone;
-      a.key0[p] = k0;
-      a.key1[p] = k0;
-      a.stamp[p] = 0u;
+      y = (int)(p / (uint32_t)job.w);
+      x = (int)(p - (uint32_t)y * (uint32_t)job.w);
+      const bool feat = job.bin[p] == 0;
+      const unsigned long long k0 = feat ? (unsigned long long)pack_yx(y, x) : kNone;
+      a.key0[job.pix_base + p] = k0;
+      a.key1[job.pix_base + p] = k0;
+      a.stamp[job.pix_base + p] = 0u;
       if (feat) {
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
           int dy, dx;
           nb_off<CONN>(k, dy, dx);
           const int qy = y + dy, qx = x + dx;
-          if (qy >= 0 && qy < a.h && qx >= 0 && qx < a.w && a.bin[(uint32_t)qy * (uint32_t)a.w + (uint32_t)qx] != 0)
+          if (qy >= 0 && qy < job.h && qx >= 0 && qx < job.w &&
+              job.bin[(uint32_t)qy * (uint32_t)job.w + (uint32_t)qx] != 0)
             c = true;
         }
       }
       contour += c ? 1u : 0u;
     }
-    // the first frontier is read by round 1: list parity 1, count slot 1
-    stage_append(s, c, item, a.lists + a.npix, a.counts + 64, a.npix, a.ovf);
+    stage_append(s, c, make_item(j, y, x), list1, a.counts + 64, a.npix, a.ovf);
   }
-  stage_flush(s, a.lists + a.npix, a.counts + 64, a.npix, a.ovf);
-  // one atomic per wave on the sharded seed counter
+  stage_flush(s, list1, a.counts + 64, a.npix, a.ovf);
   uint32_t tot = contour;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
   if (lane() == 0) stat_add(a.stats, kStatSeeds, tot);
@@ -95,10 +104,10 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
 
 template <int CONN>
 __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ unsigned long long stage_mem[kWavesPerBlock][kStageCap];
   __shared__ uint32_t nshared;
   const int w = threadIdx.x / kWave;
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
+  WaveStageT<unsigned long long> s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + w, nw = gridDim.x * kWavesPerBlock;
   uint32_t gen = 0;
   unsigned long long items = 0, updates = 0;
@@ -117,41 +126,65 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
     const unsigned long long* rd = (r & 1u) ? a.key0 : a.key1;  // buffer (r-1)&1
     unsigned long long* wr = (r & 1u) ? a.key1 : a.key0;        // buffer r&1
-    const uint32_t* list = a.lists + (size_t)(r & 1u) * a.npix;
-    uint32_t* nlist = a.lists + (size_t)((r + 1u) & 1u) * a.npix;
+    const unsigned long long* list = a.lists + (size_t)(r & 1u) * a.npix;
+    unsigned long long* nlist = a.lists + (size_t)((r + 1u) & 1u) * a.npix;
     uint32_t* ncount = a.counts + ((r + 1u) % 3u) * 64u;
     for (uint32_t base = gw * kWave; base < n; base += nw * kWave) {
       const uint32_t i = base + (uint32_t)lane();
       const bool valid = i < n;
-      int py = 0, px = 0;
-      unsigned long long sk = kNone;
+      const unsigned long long it = valid ? cload(list + i) : 0ull;
+      const uint32_t j = (uint32_t)(it >> 32);
+      const int py = (int)((uint32_t)it >> 16), px = (int)((uint32_t)it & 0xffffu);
+      int h = 1, wd = 1;
+      uint32_t pb = 0;
       if (valid) {
-        const uint32_t it = cload(list + i);
-        py = (int)(it >> 16);
-        px = (int)(it & 0xffffu);
-        const uint32_t p = (uint32_t)py * (uint32_t)a.w + (uint32_t)px;
-        sk = cload(rd + p);
-        if (r > 1u) atomic_min(wr + p, sk);  // catch up: this pixel changed in round r-1
+        const EdtJob& job = job_of(a, j);
+        h = job.h;
+        wd = job.w;
+        pb = job.pix_base;
       }
-      const uint32_t f = (uint32_t)sk;
-      const int fy = (int)(f >> 16), fx = (int)(f & 0xffffu);
+      const uint32_t p = pb + (uint32_t)py * (uint32_t)wd + (uint32_t)px;
+      // Issue every independent access of the item together (one round trip
+      // each for: its own key and its neighbours' previous keys; the atomic
+      // mins; the stamps) instead of one chain per neighbour.
+      uint32_t q[CONN];
+      bool in[CONN];
+      unsigned long long prev[CONN];
 #pragma unroll
       for (int k = 0; k < CONN; ++k) {
         int dy, dx;
         nb_off<CONN>(k, dy, dx);
         const int qy = py + dy, qx = px + dx;
-        bool fresh = false;
-        if (valid && qy >= 0 && qy < a.h && qx >= 0 && qx < a.w) {
-          const uint32_t q = (uint32_t)qy * (uint32_t)a.w + (uint32_t)qx;
-          const int ey = qy - fy, ex = qx - fx;
-          const unsigned long long cand = ((unsigned long long)(uint32_t)(ey * ey + ex * ex) << 32) | f;
-          if (cand < cload(rd + q)) {
-            const unsigned long long old = atomic_min(wr + q, cand);
-            if (cand < old) fresh = atomic_max(a.stamp + q, r) < r;
-          }
-        }
-        updates += fresh ? 1u : 0u;
-        stage_append(s, fresh, pack_yx(qy, qx), nlist, ncount, a.npix, a.ovf);
+        in[k] = valid && qy >= 0 && qy < h && qx >= 0 && qx < wd;
+        q[k] = in[k] ? pb + (uint32_t)qy * (uint32_t)wd + (uint32_t)qx : 0u;
+      }
+      const unsigned long long sk = valid ? cload(rd + p) : kNone;
+#pragma unroll
+      for (int k = 0; k < CONN; ++k) prev[k] = in[k] ? cload(rd + q[k]) : 0ull;
+      if (valid && r > 1u) atomic_min(wr + p, sk);  // catch up: this pixel changed in round r-1
+      const uint32_t f = (uint32_t)sk;
+      const int fy = (int)(f >> 16), fx = (int)(f & 0xffffu);
+      unsigned long long cand[CONN], old[CONN];
+#pragma unroll
+      for (int k = 0; k < CONN; ++k) {
+        int dy, dx;
+        nb_off<CONN>(k, dy, dx);
+        const int ey = py + dy - fy, ex = px + dx - fx;
+        cand[k] = ((unsigned long long)(uint32_t)(ey * ey + ex * ex) << 32) | f;
+        old[k] = (in[k] && cand[k] < prev[k]) ? atomic_min(wr + q[k], cand[k]) : 0ull;
+      }
+      bool fresh[CONN];
+#pragma unroll
+      for (int k = 0; k < CONN; ++k) {
+        const bool improved = in[k] && cand[k] < prev[k] && cand[k] < old[k];
+        fresh[k] = improved ? atomic_max(a.stamp + q[k], r) < r : false;
+        updates += fresh[k] ? 1u : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < CONN; ++k) {
+        int dy, dx;
+        nb_off<CONN>(k, dy, dx);
+        stage_append(s, fresh[k], make_item(j, py + dy, px + dx), nlist, ncount, a.npix, a.ovf);
       }
     }
     stage_flush(s, nlist, ncount, a.npix, a.ovf);
@@ -160,15 +193,19 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
   // Finalize: buffer (r-1)&1 holds the state after the last round.
   const unsigned long long* fin = (r & 1u) ? a.key0 : a.key1;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < a.npix; p += stride) {
-    const unsigned long long k = cload(fin + p);
-    if (k == kNone) {
-      a.sqdist[p] = -1;
-      a.nearest[p] = -1;
-    } else {
-      const uint32_t f = (uint32_t)k;
-      a.sqdist[p] = (int32_t)(k >> 32);
-      a.nearest[p] = (int32_t)((f >> 16) * (uint32_t)a.w + (f & 0xffffu));
+  for (uint32_t j = 0; j < a.njobs; ++j) {
+    const EdtJob& job = job_of(a, j);
+    const uint32_t npx = (uint32_t)job.h * (uint32_t)job.w;
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
+      const unsigned long long k = cload(fin + job.pix_base + p);
+      if (k == kNone) {
+        job.sqdist[p] = -1;
+        job.nearest[p] = -1;
+      } else {
+        const uint32_t f = (uint32_t)k;
+        job.sqdist[p] = (int32_t)(k >> 32);
+        job.nearest[p] = (int32_t)((f >> 16) * (uint32_t)job.w + (f & 0xffffu));
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) updates += __shfl_xor(updates, o);
@@ -183,13 +220,16 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
 
 int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err) {
   using namespace edt;
-  uint32_t init_blocks = (a.npix + 255u) / 256u;
-  if (init_blocks > 2048u) init_blocks = 2048u;
+  // blocks per image: enough to fill the device when spread over the images
+  uint32_t per_job = (2048u + a.njobs - 1u) / a.njobs;
+  const uint32_t avg = (a.npix / a.njobs + 255u) / 256u;
+  if (per_job > avg) per_job = avg;
+  if (per_job < 1u) per_job = 1u;
   rec->begin(4, stream);
   if (conn == 8)
-    hipLaunchKernelGGL(k_init<8>, dim3(init_blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_init<8>, dim3(per_job, a.njobs), dim3(256), 0, stream, a);
   else
-    hipLaunchKernelGGL(k_init<4>, dim3(init_blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_init<4>, dim3(per_job, a.njobs), dim3(256), 0, stream, a);
   rec->end(stream);
   if (hipGetLastError() != hipSuccess) {
     *err = "EDT init launch failed";

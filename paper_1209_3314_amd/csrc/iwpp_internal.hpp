@@ -8,38 +8,58 @@ namespace iwpp {
 
 struct GridBarrier;
 
-// Reconstruction launch arguments (device pointers, scratch owned by the context).
-struct MrArgs {
+// One reconstruction image of a launch.
+struct MrJob {
   const uint8_t* marker;
   const uint8_t* mask;
   uint8_t* out;
   int32_t h, w;
   int32_t tiles_y, tiles_x;
-  uint32_t ntiles;
-  uint32_t list_cap;     // capacity of each round's tile list (<= ntiles)
-  int32_t max_sweeps;    // sweep iterations per propagation visit before re-listing
-  int32_t seed_sweeps;   // sweep iterations per tile in the seed pass
-  uint32_t* flags;       // [2][ntiles] "already listed" per round parity
-  uint32_t* lists;       // [2][ntiles] tile lists per round parity
-  uint32_t* counts;      // [3][64] list fill levels, one per round mod 3 (256 B apart)
-  uint32_t* lost;        // [2][64] a listed tile was dropped (capacity), per parity
+  uint32_t tile_base;  // first global tile id of this image
+  uint32_t pad;
+};
+
+// Reconstruction launch arguments (device pointers, scratch owned by the context).
+// A launch processes njobs images; global tile ids run over all of them.
+struct MrArgs {
+  MrJob job0;                // the image when njobs == 1 (no table lookup)
+  const MrJob* jobs;         // [njobs] device table when njobs > 1
+  uint32_t* tile_job;        // [ntiles] image of each global tile when njobs > 1
+  uint32_t njobs;
+  uint32_t ntiles;           // total tiles over all images
+  uint32_t list_cap;         // capacity of each round's tile list (<= ntiles)
+  int32_t max_sweeps;        // sweep iterations per propagation visit before re-listing
+  int32_t seed_sweeps;       // sweep iterations per tile in the seed pass
+  uint32_t* flags;           // [2][ntiles] "already listed" per round parity
+  uint32_t* lists;           // [2][ntiles] tile lists per round parity
+  uint32_t* counts;          // [3][64] list fill levels, one per round mod 3 (256 B apart)
+  uint32_t* lost;            // [2][64] a listed tile was dropped (capacity), per parity
   GridBarrier* bar;
   unsigned long long* stats;  // [8 shards][16 fields]
 };
 
-// Distance-transform launch arguments.
-struct EdtArgs {
+// One distance-transform image of a launch.
+struct EdtJob {
   const uint8_t* bin;
   int32_t* sqdist;
   int32_t* nearest;
   int32_t h, w;
-  uint32_t npix;
-  unsigned long long* key0;  // [npix] packed (d2 << 32 | y << 16 | x), ~0 = none
-  unsigned long long* key1;  // [npix]
-  uint32_t* stamp;           // [npix] last round that listed the pixel
-  uint32_t* lists;           // [2][npix] frontier, packed (y << 16 | x)
-  uint32_t* counts;          // [3][64]
-  uint32_t* ovf;             // [64] never set: a frontier holds each pixel once
+  uint32_t pix_base;  // first global pixel id of this image
+  uint32_t pad;
+};
+
+// Distance-transform launch arguments.  Global pixel id = pix_base + y*w + x.
+struct EdtArgs {
+  EdtJob job0;                // the image when njobs == 1
+  const EdtJob* jobs;         // [njobs] device table when njobs > 1
+  uint32_t njobs;
+  uint32_t npix;              // total pixels over all images
+  unsigned long long* key0;   // [npix] packed (d2 << 32 | y << 16 | x), ~0 = none
+  unsigned long long* key1;   // [npix]
+  uint32_t* stamp;            // [npix] last round that listed the pixel
+  unsigned long long* lists;  // [2][npix] frontier items (job << 32 | y << 16 | x)
+  uint32_t* counts;           // [3][64]
+  uint32_t* ovf;              // [64] never set: a frontier holds each pixel once
   GridBarrier* bar;
   unsigned long long* stats;
 };

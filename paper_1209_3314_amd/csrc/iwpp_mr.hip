@@ -70,25 +70,43 @@ __device__ __forceinline__ uint32_t min_u8x4(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
+// A global tile id resolved to its image and tile coordinates (wave-uniform).
+struct TileRef {
+  MrJob j;
+  int ty, tx;
+};
+
+__device__ __forceinline__ TileRef tile_ref(const MrArgs& a, uint32_t t) {
+  TileRef r;
+  r.j = a.njobs == 1u ? a.job0 : a.jobs[a.tile_job[t]];
+  const uint32_t lt = t - r.j.tile_base;
+  r.ty = (int)(lt / (uint32_t)r.j.tiles_x);
+  r.tx = (int)(lt - (uint32_t)r.ty * (uint32_t)r.j.tiles_x);
+  return r;
+}
+
 // Load the (T+2) x (T+2) region of tile (ty, tx) -- the tile and its one-pixel
 // halo -- into LDS.  Pixels outside the image read as J = I = 0, which can
 // neither raise nor be raised, i.e. they are not neighbours.  In the seed pass
 // J is the marker clamped to the mask.
 template <bool kSeed>
-__device__ void load_region(const MrArgs& a, WaveLds& L, int ty, int tx) {
-  const int y0 = ty * T, x0 = tx * T;
+__device__ void load_region(const TileRef& tr, WaveLds& L) {
+  const MrJob& a = tr.j;
+  const int y0 = tr.ty * T, x0 = tr.tx * T;
   const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
   const __amdgpu_buffer_rsrc_t rj = make_rsrc(kSeed ? a.marker : a.out, total);
   const __amdgpu_buffer_rsrc_t ri = make_rsrc(a.mask, total);
+  // 66 rows x 5 items: four 16-byte chunks of the tile row, and the two halo columns.
   for (int idx = lane(); idx < kRows * 5; idx += kWave) {
     const int ry = idx / 5, item = idx - ry * 5;
     const int y = y0 - 1 + ry;
     const bool row_ok = y >= 0 && y < a.h;
+    const uint32_t rowoff = (uint32_t)(row_ok ? y : 0) * (uint32_t)a.w;
     if (item < 4) {
       const int xs = x0 + item * 16;
       v4u vj = {0u, 0u, 0u, 0u}, vi = {0u, 0u, 0u, 0u};
       if (row_ok && xs < a.w) {
-        const uint32_t off = (uint32_t)y * (uint32_t)a.w + (uint32_t)xs;
+        const uint32_t off = rowoff + (uint32_t)xs;
         if (xs + 16 <= a.w) {
           vj = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rj, off, 0, kSc1));
           vi = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ri, off, 0, kSc1));
@@ -97,10 +115,8 @@ __device__ void load_region(const MrArgs& a, WaveLds& L, int ty, int tx) {
 #pragma unroll
           for (int b = 0; b < 16; ++b) {
             if (b < nb) {
-              uint32_t jb = __builtin_amdgcn_raw_buffer_load_b8(rj, off + b, 0, kSc1);
-              uint32_t ib = __builtin_amdgcn_raw_buffer_load_b8(ri, off + b, 0, kSc1);
-              vj[b >> 2] |= jb << (8 * (b & 3));
-              vi[b >> 2] |= ib << (8 * (b & 3));
+              vj[b >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rj, off + b, 0, kSc1) << (8 * (b & 3));
+              vi[b >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(ri, off + b, 0, kSc1) << (8 * (b & 3));
             }
           }
         }
@@ -115,22 +131,16 @@ __device__ void load_region(const MrArgs& a, WaveLds& L, int ty, int tx) {
     } else {
       uint32_t jl = 0, il = 0, jr = 0, ir = 0;
       if (row_ok && x0 > 0) {
-        const uint32_t off = (uint32_t)y * (uint32_t)a.w + (uint32_t)(x0 - 1);
-        jl = __builtin_amdgcn_raw_buffer_load_b8(rj, off, 0, kSc1);
-        il = __builtin_amdgcn_raw_buffer_load_b8(ri, off, 0, kSc1);
+        jl = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + (uint32_t)(x0 - 1), 0, kSc1);
+        il = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + (uint32_t)(x0 - 1), 0, kSc1);
       }
       if (row_ok && x0 + T < a.w) {
-        const uint32_t off = (uint32_t)y * (uint32_t)a.w + (uint32_t)(x0 + T);
-        jr = __builtin_amdgcn_raw_buffer_load_b8(rj, off, 0, kSc1);
-        ir = __builtin_amdgcn_raw_buffer_load_b8(ri, off, 0, kSc1);
+        jr = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + (uint32_t)(x0 + T), 0, kSc1);
+        ir = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + (uint32_t)(x0 + T), 0, kSc1);
       }
-      if (kSeed) {
-        jl = umin(jl, il);
-        jr = umin(jr, ir);
-      }
-      L.J[lidx(ry - 1, -1)] = (uint8_t)jl;
+      L.J[lidx(ry - 1, -1)] = (uint8_t)(kSeed ? umin(jl, il) : jl);
       L.I[lidx(ry - 1, -1)] = (uint8_t)il;
-      L.J[lidx(ry - 1, T)] = (uint8_t)jr;
+      L.J[lidx(ry - 1, T)] = (uint8_t)(kSeed ? umin(jr, ir) : jr);
       L.I[lidx(ry - 1, T)] = (uint8_t)ir;
     }
   }
@@ -138,8 +148,9 @@ __device__ void load_region(const MrArgs& a, WaveLds& L, int ty, int tx) {
 }
 
 // Write the tile interior back to the image (device-coherent stores).
-__device__ void store_tile(const MrArgs& a, const WaveLds& L, int ty, int tx) {
-  const int y0 = ty * T, x0 = tx * T;
+__device__ void store_tile(const TileRef& tr, const WaveLds& L) {
+  const MrJob& a = tr.j;
+  const int y0 = tr.ty * T, x0 = tr.tx * T;
   const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
   const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, total);
   for (int idx = lane(); idx < T * 4; idx += kWave) {
@@ -161,6 +172,59 @@ __device__ void store_tile(const MrArgs& a, const WaveLds& L, int ty, int tx) {
   }
 }
 
+// One axis scan of the tile in LDS.  Vertical scans walk the rows with lane =
+// column, using the previous row's values of the three (8-conn) or one
+// (4-conn) upper/lower neighbours; horizontal scans walk the columns with
+// lane = row, using the previous column.  Steps are loaded from LDS in chunks
+// of kChunk so the wave pays one LDS latency per chunk rather than per step;
+// results are written back unconditionally and increases accumulate in `ch`.
+constexpr int kChunk = 16;
+
+template <int CONN, bool kVertical, bool kForward>
+__device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint32_t& ch) {
+  const int l = lane();
+  uint32_t prev;
+  if (kVertical)
+    prev = L.J[lidx(kForward ? -1 : T, l)];
+  else
+    prev = kForward ? hl : hr;
+  // Vertical 8-connected scans: lane 0's left neighbour and lane 63's right
+  // neighbour in the previous row are halo pixels; one LDS read per step
+  // (lane 0 reads column -1, every other lane column 64) supplies both.
+  const int halo_col = l == 0 ? -1 : T;
+#pragma unroll 1
+  for (int c = 0; c < T / kChunk; ++c) {
+    uint32_t vj[kChunk], vi[kChunk], vf[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
+      const int at = kVertical ? lidx(s, l) : lidx(l, s);
+      vj[k] = L.J[at];
+      vi[k] = L.I[at];
+      if (kVertical && CONN == 8) vf[k] = L.J[lidx(kForward ? s - 1 : s + 1, halo_col)];
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      uint32_t m = umax(vj[k], prev);
+      if (kVertical && CONN == 8) m = umax(m, umax(from_left(prev, vf[k]), from_right(prev, vf[k])));
+      const uint32_t nv = umin(m, vi[k]);
+      // Values only rise (J <= I holds throughout), so the sum of increases
+      // is nonzero iff something changed; a sum keeps the compiler from
+      // deferring per-step comparisons and holding old values live.
+      ch += nv - vj[k];
+      vj[k] = nv;
+      prev = nv;
+    }
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
+      L.J[kVertical ? lidx(s, l) : lidx(l, s)] = (uint8_t)vj[k];
+    }
+    asm volatile("" ::: "memory");  // keep chunks apart: bounded register use
+  }
+  wave_sync();
+}
+
 // Sweep the tile in LDS until a full raster + anti-raster iteration changes
 // nothing, or `max_it` iterations.  One iteration is the four axis scans of
 // Algorithm 5 in its order: row-wise forward (N^{+,0}), column-wise forward
@@ -172,80 +236,22 @@ template <int CONN>
 __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters) {
   const int l = lane();
   const uint32_t hl = L.J[lidx(l, -1)], hr = L.J[lidx(l, T)];
-  const uint32_t ctl = L.J[lidx(-1, -1)], ctr = L.J[lidx(-1, T)];
-  const uint32_t cbl = L.J[lidx(T, -1)], cbr = L.J[lidx(T, T)];
+  // Stable once four consecutive scans (one of each kind) change nothing:
+  // checked per half iteration, so a quiet backward half followed by a quiet
+  // forward half ends the visit without another full iteration.
+  bool quiet_back = false;
   for (int it = 0; it < max_it; ++it) {
-    bool ch = false;
-    {  // row-wise, left to right: lane = row
-      uint32_t prev = hl;
-#pragma unroll
-      for (int x = 0; x < T; ++x) {
-        const uint32_t v = L.J[lidx(l, x)], i = L.I[lidx(l, x)];
-        const uint32_t nv = umin(umax(v, prev), i);
-        if (nv != v) {
-          L.J[lidx(l, x)] = (uint8_t)nv;
-          ch = true;
-        }
-        prev = nv;
-      }
-    }
-    wave_sync();
-    {  // column-wise, top to bottom: lane = column
-      uint32_t prev = L.J[lidx(-1, l)];
-#pragma unroll
-      for (int y = 0; y < T; ++y) {
-        const uint32_t v = L.J[lidx(y, l)], i = L.I[lidx(y, l)];
-        uint32_t m = umax(v, prev);
-        if (CONN == 8) {
-          const uint32_t fl = y == 0 ? ctl : readlane(hl, y - 1);
-          const uint32_t fr = y == 0 ? ctr : readlane(hr, y - 1);
-          m = umax(m, umax(from_left(prev, fl), from_right(prev, fr)));
-        }
-        const uint32_t nv = umin(m, i);
-        if (nv != v) {
-          L.J[lidx(y, l)] = (uint8_t)nv;
-          ch = true;
-        }
-        prev = nv;
-      }
-    }
-    wave_sync();
-    {  // row-wise, right to left
-      uint32_t prev = hr;
-#pragma unroll
-      for (int x = T - 1; x >= 0; --x) {
-        const uint32_t v = L.J[lidx(l, x)], i = L.I[lidx(l, x)];
-        const uint32_t nv = umin(umax(v, prev), i);
-        if (nv != v) {
-          L.J[lidx(l, x)] = (uint8_t)nv;
-          ch = true;
-        }
-        prev = nv;
-      }
-    }
-    wave_sync();
-    {  // column-wise, bottom to top
-      uint32_t prev = L.J[lidx(T, l)];
-#pragma unroll
-      for (int y = T - 1; y >= 0; --y) {
-        const uint32_t v = L.J[lidx(y, l)], i = L.I[lidx(y, l)];
-        uint32_t m = umax(v, prev);
-        if (CONN == 8) {
-          const uint32_t fl = y == T - 1 ? cbl : readlane(hl, y + 1);
-          const uint32_t fr = y == T - 1 ? cbr : readlane(hr, y + 1);
-          m = umax(m, umax(from_left(prev, fl), from_right(prev, fr)));
-        }
-        const uint32_t nv = umin(m, i);
-        if (nv != v) {
-          L.J[lidx(y, l)] = (uint8_t)nv;
-          ch = true;
-        }
-        prev = nv;
-      }
-    }
-    wave_sync();
     iters++;
-    if (ballot(ch) == 0) return true;
+    uint32_t ch = 0;
+    scan<CONN, false, true>(L, hl, hr, ch);
+    scan<CONN, true, true>(L, hl, hr, ch);
+    const bool quiet_fwd = ballot(ch != 0u) == 0;
+    if (quiet_fwd && quiet_back) return true;
+    ch = 0;
+    scan<CONN, false, false>(L, hl, hr, ch);
+    scan<CONN, true, false>(L, hl, hr, ch);
+    quiet_back = ballot(ch != 0u) == 0;
+    if (quiet_fwd && quiet_back) return true;
   }
   return false;
 }
@@ -295,103 +301,91 @@ __device__ uint32_t border_marks(const WaveLds& L, uint32_t ot, uint32_t ob, uin
   return m;
 }
 
+// Put tile t on the list of parity `par` from one lane (rare or one-per-wave
+// appends outside the persistent kernel).  A tile past the capacity is
+// dropped and the list's lost flag raised.
+__device__ void list_tile(const MrArgs& a, uint32_t t, int par, uint32_t* count) {
+  if (atomic_or(a.flags + (size_t)par * a.ntiles + t, 1u) != 0u) return;
+  const uint32_t slot = atomic_add(count, 1u);
+  if (slot < a.list_cap) {
+    cstore(a.lists + (size_t)par * a.ntiles + slot, t);
+  } else {
+    cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
+    cstore(a.lost + par * 64, 1u);
+  }
+}
+
 // ---- seed pass --------------------------------------------------------------------
 // One wave per tile.  Also clears the work-list bookkeeping for this call.
 template <int CONN>
-__global__ __launch_bounds__(256) void k_seed(MrArgs a) {
+__global__ __launch_bounds__(256, 4) void k_seed(MrArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
   const int w = threadIdx.x / kWave;
   const uint32_t t = blockIdx.x * kWavesPerBlock + w;
-  if (blockIdx.x == 0 && threadIdx.x < 3 * 64) a.counts[threadIdx.x] = 0u;
-  if (blockIdx.x == 0 && threadIdx.x < 2 * 64) a.lost[threadIdx.x] = 0u;
-  if (blockIdx.x == 0) {
-    uint32_t* bar = reinterpret_cast<uint32_t*>(a.bar);
-    for (uint32_t i = threadIdx.x; i < sizeof(GridBarrier) / 4; i += blockDim.x) bar[i] = 0u;
-  }
   if (t >= a.ntiles) return;
   if (lane() == 0) {
     a.flags[t] = 0u;
     a.flags[a.ntiles + t] = 0u;
   }
-  const int ty = (int)(t / (uint32_t)a.tiles_x), tx = (int)(t % (uint32_t)a.tiles_x);
+  const TileRef tr = tile_ref(a, t);
   WaveLds& L = lds[w];
-  load_region<true>(a, L, ty, tx);
+  load_region<true>(tr, L);
   uint32_t iters = 0;
-  sweep_tile<CONN>(L, a.seed_sweeps, iters);
-  store_tile(a, L, ty, tx);
+  sweep_tile<CONN>(L, a.seed_sweeps, iters);  // a tile left unsettled is found by the dense detection
+  store_tile(tr, L);
   if (lane() == 0) stat_add(a.stats, kStatSweeps, iters);
 }
 
 // ---- seed detection -----------------------------------------------------------------
-// Dense test of every pixel of tile (ty, tx).  Returns (wave-uniform) whether
-// some pixel q of the tile can still be raised by a neighbour p, i.e.
-// J(q) < J(p) and J(q) < I(q) -- the condition of Algorithm 5, read from the
-// receiving side -- and adds to `seeds` the number of pixels p that meet
-// Algorithm 5's seed condition (some neighbour q with J(q) < J(p) and
-// J(q) < I(q)).  Loads are device-coherent: this also runs inside the
-// persistent kernel.
-struct RowVals {
-  uint32_t j, i, jl, il, jr, ir;
-};
-
-__device__ __forceinline__ RowVals load_row(const MrArgs& a, __amdgpu_buffer_rsrc_t rj, __amdgpu_buffer_rsrc_t ri,
-                                            int y, int x0) {
-  RowVals r = {0u, 0u, 0u, 0u, 0u, 0u};
-  if (y < 0 || y >= a.h) return r;
-  const uint32_t rowoff = (uint32_t)y * (uint32_t)a.w;
-  const int x = x0 + lane();
-  if (x < a.w) {
-    r.j = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + x, 0, kSc1);
-    r.i = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + x, 0, kSc1);
-  }
-  if (x0 > 0) {
-    r.jl = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + x0 - 1, 0, kSc1);
-    r.il = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + x0 - 1, 0, kSc1);
-  }
-  if (x0 + T < a.w) {
-    r.jr = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + x0 + T, 0, kSc1);
-    r.ir = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + x0 + T, 0, kSc1);
-  }
-  return r;
-}
+// Dense test of the tile in LDS (region loaded with its halo).  Returns
+// (wave-uniform) whether some pixel q of the tile can still be raised by a
+// neighbour p, i.e. J(q) < J(p) and J(q) < I(q) -- Algorithm 5's propagation
+// condition read from the receiving side -- and adds to `seeds` the number of
+// pixels p meeting Algorithm 5's seed condition (some neighbour q with
+// J(q) < J(p) and J(q) < I(q)).  Lane = column; rows are walked top to
+// bottom keeping rows y-1, y, y+1 in registers.
 
 // g(q) = J(q) if q can still rise (J(q) < I(q)), else 256 (never below J(p)).
 __device__ __forceinline__ uint32_t gval(uint32_t j, uint32_t i) { return j < i ? j : 256u; }
 
 template <int CONN>
-__device__ bool detect_tile(const MrArgs& a, int ty, int tx, uint32_t& seeds) {
-  const int y0 = ty * T, x0 = tx * T;
-  const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
-  const __amdgpu_buffer_rsrc_t rj = make_rsrc(a.out, total);
-  const __amdgpu_buffer_rsrc_t ri = make_rsrc(a.mask, total);
-  const bool col_ok = x0 + lane() < a.w;
-  RowVals up = load_row(a, rj, ri, y0 - 1, x0);
-  RowVals cur = load_row(a, rj, ri, y0, x0);
+__device__ bool lds_dirty(const WaveLds& L, uint32_t& seeds) {
+  const int l = lane();
+  const int hc = l == 0 ? -1 : T;  // fill column: lane 0 uses column -1, lane 63 column 64
+  uint32_t jp = L.J[lidx(-1, l)], ip = L.I[lidx(-1, l)], fjp = L.J[lidx(-1, hc)], fip = L.I[lidx(-1, hc)];
+  uint32_t jc = L.J[lidx(0, l)], ic = L.I[lidx(0, l)], fjc = L.J[lidx(0, hc)], fic = L.I[lidx(0, hc)];
   bool any = false;
-  const int rows = a.h - y0 < T ? a.h - y0 : T;
-  for (int y = 0; y < rows; ++y) {
-    RowVals dn = load_row(a, rj, ri, y0 + y + 1, x0);
-    // receiving side: largest neighbour value
-    uint32_t m = umax(umax(up.j, dn.j), umax(from_left(cur.j, cur.jl), from_right(cur.j, cur.jr)));
-    // sending side: smallest raisable neighbour value
-    uint32_t g = umin(umin(gval(up.j, up.i), gval(dn.j, dn.i)),
-                      umin(from_left(gval(cur.j, cur.i), gval(cur.jl, cur.il)),
-                           from_right(gval(cur.j, cur.i), gval(cur.jr, cur.ir))));
-    if (CONN == 8) {
-      m = umax(m, umax(umax(from_left(up.j, up.jl), from_right(up.j, up.jr)),
-                       umax(from_left(dn.j, dn.jl), from_right(dn.j, dn.jr))));
-      g = umin(g, umin(umin(from_left(gval(up.j, up.i), gval(up.jl, up.il)),
-                            from_right(gval(up.j, up.i), gval(up.jr, up.ir))),
-                       umin(from_left(gval(dn.j, dn.i), gval(dn.jl, dn.il)),
-                            from_right(gval(dn.j, dn.i), gval(dn.jr, dn.ir)))));
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int c = 0; c < T / kChunk; ++c) {
+    uint32_t nj[kChunk], ni[kChunk], nfj[kChunk], nfi[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int y = c * kChunk + k + 1;
+      nj[k] = L.J[lidx(y, l)];
+      ni[k] = L.I[lidx(y, l)];
+      nfj[k] = L.J[lidx(y, hc)];
+      nfi[k] = L.I[lidx(y, hc)];
     }
-    const bool raisable = col_ok && cur.j < umin(m, cur.i);
-    const bool seed = col_ok && cur.j > g;
-    any |= raisable;
-    seeds += (uint32_t)__popcll(ballot(seed));
-    up = cur;
-    cur = dn;
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const uint32_t jn = nj[k], in = ni[k], fjn = nfj[k], fin = nfi[k];
+      uint32_t m = umax(umax(jp, jn), umax(from_left(jc, fjc), from_right(jc, fjc)));
+      const uint32_t gc = gval(jc, ic), gfc = gval(fjc, fic);
+      uint32_t g = umin(umin(gval(jp, ip), gval(jn, in)), umin(from_left(gc, gfc), from_right(gc, gfc)));
+      if (CONN == 8) {
+        m = umax(m, umax(umax(from_left(jp, fjp), from_right(jp, fjp)), umax(from_left(jn, fjn), from_right(jn, fjn))));
+        const uint32_t gp = gval(jp, ip), gfp = gval(fjp, fip), gn = gval(jn, in), gfn = gval(fjn, fin);
+        g = umin(g, umin(umin(from_left(gp, gfp), from_right(gp, gfp)), umin(from_left(gn, gfn), from_right(gn, gfn))));
+      }
+      any |= jc < umin(m, ic);
+      cnt += (uint32_t)__popcll(ballot(jc > g));
+      jp = jc; ip = ic; fjp = fjc; fip = fic;
+      jc = jn; ic = in; fjc = fjn; fic = fin;
+    }
+    asm volatile("" ::: "memory");
   }
+  seeds += cnt;
   return ballot(any) != 0;
 }
 
@@ -437,23 +431,66 @@ __device__ __forceinline__ void mark_tiles(const MrArgs& a, WaveStage& s, bool p
 
 template <int CONN>
 __global__ __launch_bounds__(256) void k_detect(MrArgs a) {
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ WaveLds lds[kWavesPerBlock];
   const int w = threadIdx.x / kWave;
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
-  const uint32_t gw = blockIdx.x * kWavesPerBlock + w, nw = gridDim.x * kWavesPerBlock;
+  const uint32_t t = blockIdx.x * kWavesPerBlock + w;
+  if (t >= a.ntiles) return;
+  const TileRef tr = tile_ref(a, t);
+  WaveLds& L = lds[w];
+  load_region<false>(tr, L);
   uint32_t seeds = 0;
-  for (uint32_t t = gw; t < a.ntiles; t += nw) {
-    const int ty = (int)(t / (uint32_t)a.tiles_x), tx = (int)(t % (uint32_t)a.tiles_x);
-    const bool any = detect_tile<CONN>(a, ty, tx, seeds);
-    mark_tiles(a, s, any && lane() == 0, t, 0, a.counts);
+  const bool dirty = lds_dirty<CONN>(L, seeds);
+  if (lane() == 0) {
+    stat_add(a.stats, kStatSeeds, seeds);
+    if (dirty) list_tile(a, t, 0, a.counts);
   }
-  tile_flush(s, a.lists, a.counts, a.list_cap, a.flags, a.lost);
-  if (lane() == 0) stat_add(a.stats, kStatSeeds, seeds);
 }
 
 // ---- persistent propagation -----------------------------------------------------------
+// One tile visit: load the tile and its halo, sweep to local stability, write
+// back, and list the neighbouring tiles a border change can raise (and the
+// tile itself if the sweep cap stopped it).  With `check`, a tile that has no
+// raisable pixel is left alone.
 template <int CONN>
-__global__ __launch_bounds__(256) void k_propagate(MrArgs a) {
+__device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t, bool check, int npar,
+                           uint32_t* ncount, uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
+  const TileRef tr = tile_ref(a, t);
+  load_region<false>(tr, L);
+  if (check && !lds_dirty<CONN>(L, seeds)) return;
+  const int l = lane();
+  const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
+  const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
+  uint32_t it = 0;
+  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it);
+  iters += it;
+  visits++;
+  // A visit that ends within its first iteration changed nothing; one that
+  // ends later (or is cut off) changed something.
+  const bool changed = it > 1 || !stable;
+  if (changed) store_tile(tr, L);
+  const uint32_t m = changed ? border_marks<CONN>(L, ot, ob, ol, orr) : 0u;
+  // Candidate tiles in lanes 0..8 (8 = this tile when not yet stable).
+  int dy = 0, dx = 0;
+  bool want = false;
+  if (l < 8) {
+    // bit order of border_marks: top, bottom, left, right, tl, tr, bl, br
+    want = (m >> l) & 1u;
+    dy = l < 2 ? (l == 0 ? -1 : 1) : (l < 4 ? 0 : (l < 6 ? -1 : 1));
+    dx = l < 2 ? 0 : (l < 4 ? (l == 2 ? -1 : 1) : ((l & 1) ? 1 : -1));
+  } else if (l == 8) {
+    want = !stable;
+  }
+  const int ny = tr.ty + dy, nx = tr.tx + dx;
+  want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
+  mark_tiles(a, s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), npar, ncount);
+}
+
+// Rounds: round r visits the tiles of list r (parity r&1) and lists the tiles
+// to visit in round r+1.  A round whose list lost tiles to the capacity is
+// replaced by a full round that visits every tile holding a raisable pixel
+// (all flags cleared first), which restarts from the current image.
+template <int CONN>
+__global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
   __shared__ uint32_t decision[2];
@@ -462,87 +499,49 @@ __global__ __launch_bounds__(256) void k_propagate(MrArgs a) {
   WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + w, nw = gridDim.x * kWavesPerBlock;
   uint32_t gen = 0;
-  uint32_t visits = 0, iters = 0, rounds = 0, restarts = 0;
+  uint32_t visits = 0, iters = 0, rounds = 0, restarts = 0, seeds = 0;
   for (uint32_t r = 0;; ++r) {
-    const int par = (int)(r & 1u);
+    const int par = (int)(r & 1u), npar = 1 - par;
     uint32_t* count = a.counts + (r % 3u) * 64u;
-    // Decide (identically in every workgroup) whether this round's list must be
-    // rebuilt: a drop was recorded for it, or it is empty while a drop is still
-    // pending for the other parity.  Nothing writes these words between the
-    // last barrier and this read unless the decision is "rebuild".
+    // Every workgroup reads the same words: nothing writes them between the
+    // previous barrier and this read (round r appends to list r+1).
     if (threadIdx.x == 0) {
-      const uint32_t n = cload(count);
-      const uint32_t lost_here = cload(a.lost + par * 64), lost_other = cload(a.lost + (1 - par) * 64);
-      decision[0] = n;
-      decision[1] = (lost_here != 0u) || (n == 0u && lost_other != 0u);
+      decision[0] = cload(count);
+      decision[1] = cload(a.lost + par * 64);
     }
     __syncthreads();
     uint32_t n = decision[0];
-    if (decision[1]) {
-      if (!grid_barrier(a.bar, gen, a.stats)) break;
+    const bool full = decision[1] != 0u;
+    if (!full && n == 0u) break;
+    if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
+      if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
+      break;
+    }
+    if (full) {
+      if (!grid_barrier(a.bar, gen, a.stats)) break;  // everyone has read the decision
       for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2u * a.ntiles; i += gridDim.x * blockDim.x)
         cstore(a.flags + i, 0u);
       if (blockIdx.x == 0 && threadIdx.x == 0) {
-        cstore(count, 0u);
         cstore(a.lost, 0u);
         cstore(a.lost + 64, 0u);
         restarts++;
       }
       if (!grid_barrier(a.bar, gen, a.stats)) break;
-      uint32_t seeds = 0;
-      for (uint32_t t = gw; t < a.ntiles; t += nw) {
-        const int ty = (int)(t / (uint32_t)a.tiles_x), tx = (int)(t % (uint32_t)a.tiles_x);
-        const bool any = detect_tile<CONN>(a, ty, tx, seeds);
-        mark_tiles(a, s, any && lane() == 0, t, par, count);
-      }
-      tile_flush(s, a.lists + (size_t)par * a.ntiles, count, a.list_cap, a.flags + (size_t)par * a.ntiles,
-                 a.lost + par * 64);
-      if (!grid_barrier(a.bar, gen, a.stats)) break;
-      if (threadIdx.x == 0) decision[0] = cload(count);
-      __syncthreads();
-      n = decision[0];
     }
-    if (n == 0u) break;
-    if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
-      if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
-      break;
-    }
-    if (n > a.list_cap) n = a.list_cap;
     // The count of round r+2 is reused: clear it now (it was last read in round
     // r-1, and is next appended to in round r+1, after this round's barrier).
     if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
-    const int npar = 1 - par;
     uint32_t* ncount = a.counts + ((r + 1u) % 3u) * 64u;
-    const uint32_t* list = a.lists + (size_t)par * a.ntiles;
-    for (uint32_t i = gw; i < n; i += nw) {
-      const uint32_t t = cload(list + i);
-      if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
-      const int ty = (int)(t / (uint32_t)a.tiles_x), tx = (int)(t % (uint32_t)a.tiles_x);
-      load_region<false>(a, L, ty, tx);
-      const int l = lane();
-      const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
-      const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
-      uint32_t it = 0;
-      const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it);
-      iters += it;
-      visits++;
-      const bool changed = it > 1 || !stable;  // the first iteration changed something
-      if (changed) store_tile(a, L, ty, tx);
-      uint32_t m = changed ? border_marks<CONN>(L, ot, ob, ol, orr) : 0u;
-      // Candidate tiles in lanes 0..8 (8 = this tile when not yet stable).
-      int dy = 0, dx = 0;
-      bool want = false;
-      if (l < 8) {
-        // bit order of border_marks: top, bottom, left, right, tl, tr, bl, br
-        want = (m >> l) & 1u;
-        dy = l < 2 ? (l == 0 ? -1 : 1) : (l < 4 ? 0 : (l < 6 ? -1 : 1));
-        dx = l < 2 ? 0 : (l < 4 ? (l == 2 ? -1 : 1) : ((l & 1) ? 1 : -1));
-      } else if (l == 8) {
-        want = !stable;
+    if (full) {
+      for (uint32_t t = gw; t < a.ntiles; t += nw) visit_tile<CONN>(a, L, s, t, true, npar, ncount, visits, iters, seeds);
+    } else {
+      if (n > a.list_cap) n = a.list_cap;
+      const uint32_t* list = a.lists + (size_t)par * a.ntiles;
+      for (uint32_t i = gw; i < n; i += nw) {
+        const uint32_t t = cload(list + i);
+        if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
+        visit_tile<CONN>(a, L, s, t, false, npar, ncount, visits, iters, seeds);
       }
-      const int ny = ty + dy, nx = tx + dx;
-      want = want && ny >= 0 && ny < a.tiles_y && nx >= 0 && nx < a.tiles_x;
-      mark_tiles(a, s, want, (uint32_t)(ny * a.tiles_x + nx), npar, ncount);
     }
     tile_flush(s, a.lists + (size_t)npar * a.ntiles, ncount, a.list_cap, a.flags + (size_t)npar * a.ntiles,
                a.lost + npar * 64);
@@ -559,12 +558,32 @@ __global__ __launch_bounds__(256) void k_propagate(MrArgs a) {
   }
 }
 
+// Image of every global tile, by binary search over the images' first tiles.
+__global__ void k_tile_job(const MrJob* jobs, uint32_t njobs, uint32_t* tile_job, uint32_t ntiles) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = njobs;  // last job with tile_base <= t
+    while (hi - lo > 1u) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].tile_base <= t) lo = mid; else hi = mid;
+    }
+    tile_job[t] = lo;
+  }
+}
+
 }  // namespace mr
 
 // ---- host-side launch -----------------------------------------------------------------
 int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err) {
   using namespace mr;
   const uint32_t seed_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (a.njobs > 1u) {
+    const uint32_t b = (a.ntiles + 255u) / 256u;
+    hipLaunchKernelGGL(k_tile_job, dim3(b < 1024u ? b : 1024u), dim3(256), 0, stream, a.jobs, a.njobs, a.tile_job, a.ntiles);
+    if (hipGetLastError() != hipSuccess) {
+      *err = "tile map launch failed";
+      return -1;
+    }
+  }
   rec->begin(1, stream);
   if (conn == 8)
     hipLaunchKernelGGL(k_seed<8>, dim3(seed_blocks), dim3(256), 0, stream, a);
@@ -575,7 +594,7 @@ int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stre
     *err = "seed-pass launch failed";
     return -1;
   }
-  uint32_t det_blocks = seed_blocks < 2048u ? seed_blocks : 2048u;
+  const uint32_t det_blocks = seed_blocks;
   rec->begin(2, stream);
   if (conn == 8)
     hipLaunchKernelGGL(k_detect<8>, dim3(det_blocks), dim3(256), 0, stream, a);
