@@ -73,6 +73,139 @@ def algorithmic_bytes(part: str, kernel: str, n: int, q_ref: int, conn: int) -> 
     return 0.0
 
 
+def _gen_tile(i):
+    from paper_1209_3314_amd import synth
+
+    return synth.tile_inputs(synth.batch_tile_spec(i))
+
+
+def _oracle_tile(args):
+    import numpy as np
+
+    import oracle
+
+    spec, x, got = args
+    if spec["op"] == "mr":
+        return bool(np.array_equal(oracle.mr_fh(x[0], x[1], spec["conn"]), got[0]))
+    s, n = oracle.edt_rounds(x, spec["conn"])
+    return bool(np.array_equal(s, got[0]) and np.array_equal(n, got[1]))
+
+
+def pool_workers() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def batch_leg(ctx, torch, np, pool, gen, ntiles: int, check: bool) -> dict:
+    """The mixed batch of `ntiles` tiles (sides uniform in [512, 4096], even
+    tiles reconstruction, odd tiles EDT, all 8-connected): one plain call per
+    tile on one stream, against one batched call and against one replay of the
+    batch captured as a HIP graph.  All tiles are submitted together at t = 0;
+    a tile's latency is the time from t = 0 until its result is complete (plain:
+    its call's end on the stream; batched: the end of the batch).  Inputs are
+    resident in HBM; outputs of the three runs are compared with each other on
+    the device and, with `check`, with the oracle (`pool`, forked before the
+    process touched the GPU; `gen` is the pending generation of the tiles)."""
+    from paper_1209_3314_amd import synth
+
+    specs = [synth.batch_tile_spec(i) for i in range(ntiles)]
+    t = time.time()
+    host = gen.get()
+    log(f"batch: tiles ready after {time.time() - t:.1f}s more")
+    dev = torch.device("cuda", 0)
+    jobs = []
+    px = 0
+    for spec, x in zip(specs, host):
+        h, w = spec["h"], spec["w"]
+        px += h * w
+        if spec["op"] == "mr":
+            jobs.append({"op": "recon", "conn": spec["conn"], "marker": torch.from_numpy(x[0]).to(dev),
+                         "mask": torch.from_numpy(x[1]).to(dev),
+                         "out": torch.empty((h, w), dtype=torch.uint8, device=dev)})
+        else:
+            jobs.append({"op": "edt", "conn": spec["conn"], "binary": torch.from_numpy(x).to(dev),
+                         "sqdist": torch.empty((h, w), dtype=torch.int32, device=dev),
+                         "nearest": torch.empty((h, w), dtype=torch.int32, device=dev)})
+    outs = lambda j: [j["out"]] if j["op"] == "recon" else [j["sqdist"], j["nearest"]]
+
+    def plain():
+        for j in jobs:
+            if j["op"] == "recon":
+                ctx.morph_recon(j["marker"], j["mask"], j["conn"], out=j["out"])
+            else:
+                ctx.edt(j["binary"], j["conn"], out=(j["sqdist"], j["nearest"]))
+
+    # warm up each form once
+    plain()
+    ctx.run_batch(jobs)
+    g = ctx.batch_graph(jobs)
+    g.launch()
+    torch.cuda.synchronize()
+    ctx.profile_read()
+
+    # plain: an event after every tile gives each tile's completion time
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(ntiles + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i, j in enumerate(jobs):
+        if j["op"] == "recon":
+            ctx.morph_recon(j["marker"], j["mask"], j["conn"], out=j["out"])
+        else:
+            ctx.edt(j["binary"], j["conn"], out=(j["sqdist"], j["nearest"]))
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    done_plain = np.array([ev[0].elapsed_time(e) for e in ev[1:]])
+    ref = [[o.clone() for o in outs(j)] for j in jobs]
+
+    def timed(fn):
+        for j in jobs:
+            for o in outs(j):
+                o.fill_(-3 if o.dtype == torch.int32 else 3)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        same = all(torch.equal(o, r) for j, rr in zip(jobs, ref) for o, r in zip(outs(j), rr))
+        return a.elapsed_time(b), same
+
+    batch_ms, batch_same = timed(lambda: ctx.run_batch(jobs))
+    bstats = ctx.stats()
+    graph_ms, graph_same = timed(lambda: g.launch())
+    gstats = g.stats()
+    g.close()
+    ctx.profile_read()
+    plain_ms = float(done_plain[-1])
+    res = {
+        "tiles": ntiles, "pixels": px, "workload": "256-tile mixed batch: sides U[512,4096], even tiles reconstruction "
+        "(disk density of the 512^2 workload, offset U[16,64]), odd tiles EDT (coverage U[0.1,0.5]), conn 8, seeds 1000+i",
+        "plain_ms": round(plain_ms, 3), "batch_ms": round(batch_ms, 3), "graph_ms": round(graph_ms, 3),
+        "plain_mpix_s": round(px / plain_ms / 1e3, 1), "batch_mpix_s": round(px / batch_ms / 1e3, 1),
+        "graph_mpix_s": round(px / graph_ms / 1e3, 1),
+        "speedup_batch": round(plain_ms / batch_ms, 3), "speedup_graph": round(plain_ms / graph_ms, 3),
+        "latency_ms": {"plain_p50": round(float(np.percentile(done_plain, 50)), 3),
+                       "plain_p99": round(float(np.percentile(done_plain, 99)), 3),
+                       "batch_p50": round(batch_ms, 3), "batch_p99": round(batch_ms, 3),
+                       "graph_p50": round(graph_ms, 3), "graph_p99": round(graph_ms, 3)},
+        "plain_tile_ms": {"p50": round(float(np.percentile(np.diff(done_plain, prepend=0.0), 50)), 3),
+                          "p99": round(float(np.percentile(np.diff(done_plain, prepend=0.0), 99)), 3)},
+        "batch_equals_plain": bool(batch_same), "graph_equals_plain": bool(graph_same),
+        "batch_status": bstats["status"], "graph_status": gstats["status"],
+        "bit_exact": None, "cpu_baseline": None,
+    }
+    if check:
+        got = [[r.cpu().numpy() for r in rr] for rr in ref]
+        nw = pool_workers()
+        t = time.perf_counter()
+        ok = pool.map(_oracle_tile, list(zip(specs, host, got)), chunksize=1)
+        cpu_s = time.perf_counter() - t
+        res["bit_exact"] = bool(all(ok))
+        res["cpu_baseline"] = {"value": round(px / cpu_s / 1e6, 2), "unit": "Mpixel/s", "cores": nw, "kind": "oracle",
+                               "sample": f"all {ntiles} tiles, oracle in a pool of {nw} processes ({cpu_s:.1f} s)"}
+    log(f"batch: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +213,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle run (then no bit-exactness check and no work counts)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-tile batched leg")
+    ap.add_argument("--batch-tiles", type=int, default=256, help="tiles in the batched leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -100,6 +235,15 @@ def main():
               "(independent tiles would shard one per GPU; see DESIGN.md). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    pool = gen = None
+    if not args.no_batch:
+        # Workers are forked before this process initialises the GPU; the batch
+        # tiles are generated while the single-image part runs.
+        from multiprocessing import get_context
+
+        pool = get_context("fork").Pool(pool_workers())
+        gen = pool.map_async(_gen_tile, range(args.batch_tiles), chunksize=1)
 
     import numpy as np
     import torch
@@ -220,6 +364,12 @@ def main():
                                  "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "mpix_s": round(n / (ms * 1e-3) / 1e6, 1)}
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(ctx, torch, np, pool, gen, args.batch_tiles, check=not args.no_cpu_baseline)
+        pool.close()
+        pool.join()
+
     px = 2 * n_mr + n_edt
     value = px / (ms_per_step * 1e-3) / 1e6
     line = {
@@ -233,6 +383,7 @@ def main():
         "per_op": op_roofline, "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
         "wall_ms_per_step": round(wall_ms / args.steps, 4),
         "work": {"q_ref": q_ref, "gpu": gpu_stats},
+        "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

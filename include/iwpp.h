@@ -39,6 +39,8 @@ extern "C" {
 #endif
 
 typedef struct iwpp_ctx iwpp_ctx;
+typedef struct iwpp_graph iwpp_graph;
+typedef struct iwpp_server iwpp_server;
 
 typedef enum {
   IWPP_OK = 0,
@@ -68,7 +70,11 @@ typedef struct {
    * iwpp_profile_read can report per-kernel device times.  Costs two event
    * records per launch. */
   int32_t profile;
-  int32_t reserved[7];
+  /* Cap on sweep iterations per tile in the reconstruction seed pass (the
+   * number of raster/anti-raster scan pairs before the queue takes over; the
+   * paper varies the number of initial scans in Table 1). */
+  int32_t mr_seed_sweeps;
+  int32_t reserved[6];
 } iwpp_options;
 
 /* Counters of the last compute call on a context (see iwpp_get_stats). */
@@ -186,12 +192,97 @@ enum { IWPP_OP_RECON = 1, IWPP_OP_EDT = 2 };
  *   jobs : host array of n descriptors (copied before the call returns)
  *   n    : >= 1
  * Each job obeys the rules of iwpp_morph_recon_u8 / iwpp_edt; in addition no
- * output may overlap another job's input or output.  A recon group must have
- * fewer than 2^32 pixels per image; an EDT group fewer than 2^32 pixels in
- * total.  Counters from iwpp_get_stats cover the whole batch.
+ * output may overlap another job's input or output.  Counters from
+ * iwpp_get_stats cover the whole batch.
  * Errors: IWPP_EINVAL (bad job: the message names its index), IWPP_ENOMEM,
  * IWPP_EDEVICE. */
 int32_t iwpp_run_batch(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, void* stream);
+
+/* Replace the context's options for later calls (for per-call tuning).
+ * Errors: IWPP_EINVAL for NULL or negative fields. */
+int32_t iwpp_set_options(iwpp_ctx* ctx, const iwpp_options* opt);
+
+/* Capture a batch (same rules as iwpp_run_batch) into a HIP graph that can be
+ * replayed with one launch: the job tables are uploaded once, every kernel of
+ * every group is recorded, and the graph owns its scratch memory and counters,
+ * so replays do not depend on the context's later calls.  The graph reads and
+ * writes the buffers named in `jobs` on every launch.  Inside the graph the
+ * persistent kernels are plain launches of a device-filling grid: launch the
+ * graph when the device is not busy with other work (if the grid cannot all be
+ * resident, the kernels stop with status IWPP_EDEVICE rather than waiting).
+ * Errors: as iwpp_run_batch; IWPP_EDEVICE if capture is not possible. */
+int32_t iwpp_batch_graph_create(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, iwpp_graph** out);
+
+/* Enqueue one replay of the graph on `stream` (hipStream_t as void*). */
+int32_t iwpp_batch_graph_launch(iwpp_graph* graph, void* stream);
+
+/* Counters of the graph's last replay (synchronises with its stream). */
+int32_t iwpp_batch_graph_stats(iwpp_graph* graph, iwpp_stats* out);
+
+/* Free the graph and its memory (waits for the device).  NULL is allowed. */
+void iwpp_batch_graph_destroy(iwpp_graph* graph);
+
+/* ---- serving ------------------------------------------------------------
+ * A request loop on one context, after the paper's demand-driven runtime that
+ * hands independent tiles to whichever device is free in arrival order
+ * (Sec. 4).  Jobs come with HOST buffers; a worker thread admits them in
+ * arrival order while the device-memory budget and the in-flight slot limit
+ * allow, uploads them on a copy stream, runs every admitted job that is not
+ * yet running as one batch (continuous batching: jobs that arrive while a
+ * batch runs form the next one), downloads the outputs on a second copy
+ * stream and timestamps completion.  Results are the same bytes as the single
+ * image calls.  While a server runs, the other calls on its context return
+ * IWPP_EBUSY. */
+typedef struct {
+  /* Device memory the server holds: admitted jobs' buffers plus one scratch
+   * area shared by the batches (0 = 64 GiB). */
+  int64_t hbm_budget_bytes;
+  /* Part of the budget kept as the batches' scratch area; it bounds the
+   * pixels of one batch (0 = a quarter of the budget). */
+  int64_t scratch_bytes;
+  int32_t max_inflight; /* admitted jobs not yet complete (0 = 4096) */
+  int32_t max_batch;    /* jobs per launch; 1 = one job per launch (0 = 512) */
+  int32_t reserved[6];
+} iwpp_server_options;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t batches;        /* launches (batches) so far */
+  int64_t max_batch_jobs; /* largest batch */
+  int64_t peak_bytes;     /* high-water mark of device memory in use */
+  int64_t admitted_now;   /* admitted, not complete */
+  int64_t queued_now;     /* submitted, not admitted */
+  int64_t reserved[4];
+} iwpp_server_stats;
+
+enum { IWPP_JOB_QUEUED = 0, IWPP_JOB_ADMITTED = 1, IWPP_JOB_RUNNING = 2, IWPP_JOB_DONE = 3, IWPP_JOB_FAILED = 4 };
+
+/* Allocate the budget on the context's device and start the worker thread.
+ * Errors: IWPP_EINVAL (bad options), IWPP_EBUSY (already serving),
+ * IWPP_ENOMEM (the budget cannot be allocated). */
+int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_server** out);
+
+/* Queue one job.  `job` has the layout of iwpp_run_batch's jobs but HOST
+ * pointers (page-locked memory lets the copies overlap the computation); the
+ * caller must not change the inputs or read the outputs before the job is
+ * done.  `arrival_ns` is the request's arrival time on CLOCK_MONOTONIC (0 =
+ * now); latency is measured from it.  Errors: IWPP_EINVAL (bad job, or one
+ * that can never fit the budget), IWPP_EBUSY (stopping). */
+int32_t iwpp_server_submit(iwpp_server* server, const iwpp_job* job, int64_t arrival_ns, uint64_t* ticket);
+
+/* State of a ticket (IWPP_JOB_*) and, once done or failed, its latency:
+ * completion of the output download minus arrival, in ms (else -1). */
+int32_t iwpp_server_poll(iwpp_server* server, uint64_t ticket, int32_t* state, double* latency_ms);
+
+/* Wait until every submitted job is done or failed (timeout_ms < 0: no
+ * limit).  IWPP_EBUSY on timeout, IWPP_EDEVICE if a job failed. */
+int32_t iwpp_server_drain(iwpp_server* server, int64_t timeout_ms);
+
+int32_t iwpp_server_get_stats(iwpp_server* server, iwpp_server_stats* out);
+
+/* Finish every submitted job, stop the worker and free the budget; the
+ * context is usable again.  IWPP_EDEVICE if any job failed. */
+int32_t iwpp_server_stop(iwpp_server* server);
 
 /* Per-kernel device times recorded since the previous read (needs
  * iwpp_options.profile).  Synchronises with every stream the recorded

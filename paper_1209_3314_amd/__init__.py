@@ -17,7 +17,7 @@ import threading
 
 from . import _lib
 
-__all__ = ["Context", "IwppError", "morph_recon", "edt", "last_stats"]
+__all__ = ["Context", "BatchGraph", "Server", "IwppError", "morph_recon", "edt", "last_stats"]
 
 
 class IwppError(RuntimeError):
@@ -55,13 +55,10 @@ class Context:
     context per device and the current torch stream."""
 
     def __init__(self, device: int = 0, mr_list_capacity: int = 0, mr_max_sweeps: int = 0,
-                 persistent_blocks: int = 0, profile: bool = False):
+                 persistent_blocks: int = 0, profile: bool = False, mr_seed_sweeps: int = 0):
         lib = _lib.load()
-        opt = _lib.Options()
-        opt.mr_list_capacity = int(mr_list_capacity)
-        opt.mr_max_sweeps = int(mr_max_sweeps)
-        opt.persistent_blocks = int(persistent_blocks)
-        opt.profile = 1 if profile else 0
+        opt = _options(mr_list_capacity=mr_list_capacity, mr_max_sweeps=mr_max_sweeps,
+                       persistent_blocks=persistent_blocks, profile=profile, mr_seed_sweeps=mr_seed_sweeps)
         h = ctypes.c_void_p()
         rc = lib.iwpp_create(int(device), ctypes.byref(opt), ctypes.byref(h))
         if rc != _lib.IWPP_OK:
@@ -69,6 +66,22 @@ class Context:
         self._lib = lib
         self._h = h
         self.device = int(device)
+        self.options = {"mr_list_capacity": int(mr_list_capacity), "mr_max_sweeps": int(mr_max_sweeps),
+                        "persistent_blocks": int(persistent_blocks), "profile": bool(profile),
+                        "mr_seed_sweeps": int(mr_seed_sweeps)}
+
+    def set_options(self, **kw) -> None:
+        """Change tuning options (same names as the constructor) for later
+        calls; options not named keep their value.  Results never depend on
+        them."""
+        unknown = set(kw) - set(self.options)
+        if unknown:
+            raise TypeError(f"unknown options {sorted(unknown)}")
+        new = dict(self.options, **kw)
+        rc = self._lib.iwpp_set_options(self._h, ctypes.byref(_options(**new)))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        self.options = new
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -132,40 +145,21 @@ class Context:
         dict: reconstruction ``{"op": "recon", "marker", "mask", "out", "conn"}``
         or EDT ``{"op": "edt", "binary", "sqdist", "nearest", "conn"}`` with
         tensors on this context's device (outputs preallocated)."""
-        torch = _torch()
-        if not jobs:
-            raise ValueError("empty batch")
-        arr = (_lib.Job * len(jobs))()
-        dev = None
-        for i, j in enumerate(jobs):
-            conn = int(j.get("conn", 8))
-            if conn not in (4, 8):
-                raise ValueError(f"job {i}: conn must be 4 or 8")
-            if j["op"] == "recon":
-                _check_image(j["mask"], f"job {i} mask", torch.uint8, dev)
-                dev = j["mask"].device
-                _check_image(j["marker"], f"job {i} marker", torch.uint8, dev)
-                _check_image(j["out"], f"job {i} out", torch.uint8, dev)
-                if not (j["marker"].shape == j["mask"].shape == j["out"].shape):
-                    raise ValueError(f"job {i}: shapes differ")
-                h, w = j["mask"].shape
-                arr[i] = _lib.Job(_lib.IWPP_OP_RECON, conn, h, w, j["marker"].data_ptr(), j["mask"].data_ptr(),
-                                  j["out"].data_ptr(), None)
-            elif j["op"] == "edt":
-                _check_image(j["binary"], f"job {i} binary", torch.uint8, dev)
-                dev = j["binary"].device
-                _check_image(j["sqdist"], f"job {i} sqdist", torch.int32, dev)
-                _check_image(j["nearest"], f"job {i} nearest", torch.int32, dev)
-                if not (j["binary"].shape == j["sqdist"].shape == j["nearest"].shape):
-                    raise ValueError(f"job {i}: shapes differ")
-                h, w = j["binary"].shape
-                arr[i] = _lib.Job(_lib.IWPP_OP_EDT, conn, h, w, j["binary"].data_ptr(), None,
-                                  j["sqdist"].data_ptr(), j["nearest"].data_ptr())
-            else:
-                raise ValueError(f"job {i}: op must be 'recon' or 'edt'")
+        arr, dev = _marshal_jobs(jobs)
         rc = self._lib.iwpp_run_batch(self._h, arr, len(jobs), self._stream(dev))
         if rc != _lib.IWPP_OK:
             self._err(rc)
+
+    def batch_graph(self, jobs: list) -> "BatchGraph":
+        """Capture `jobs` (same form as run_batch) into a replayable HIP graph.
+        The graph keeps reading and writing the jobs' tensors: keep them alive
+        and in place while the graph is used."""
+        arr, dev = _marshal_jobs(jobs)
+        g = ctypes.c_void_p()
+        rc = self._lib.iwpp_batch_graph_create(self._h, arr, len(jobs), ctypes.byref(g))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return BatchGraph(self, g, dev, [t for j in jobs for t in j.values() if not isinstance(t, (int, str))])
 
     def profile_read(self) -> list:
         """(kernel name, device ms) for every launch since the last read, in
@@ -182,8 +176,209 @@ class Context:
         rc = self._lib.iwpp_get_stats(self._h, ctypes.byref(st))
         if rc != _lib.IWPP_OK:
             self._err(rc)
-        return {"status": st.status, "op": st.op, "seeds": st.seeds, "items": st.items, "sweeps": st.sweeps,
-                "rounds": st.rounds, "updates": st.updates, "overflow_restarts": st.overflow_restarts}
+        return _stats_dict(st)
+
+
+def _options(mr_list_capacity=0, mr_max_sweeps=0, persistent_blocks=0, profile=False, mr_seed_sweeps=0):
+    opt = _lib.Options()
+    opt.mr_list_capacity = int(mr_list_capacity)
+    opt.mr_max_sweeps = int(mr_max_sweeps)
+    opt.persistent_blocks = int(persistent_blocks)
+    opt.profile = 1 if profile else 0
+    opt.mr_seed_sweeps = int(mr_seed_sweeps)
+    return opt
+
+
+def _marshal_jobs(jobs: list):
+    torch = _torch()
+    if not jobs:
+        raise ValueError("empty batch")
+    arr = (_lib.Job * len(jobs))()
+    dev = None
+    for i, j in enumerate(jobs):
+        conn = int(j.get("conn", 8))
+        if conn not in (4, 8):
+            raise ValueError(f"job {i}: conn must be 4 or 8")
+        if j["op"] == "recon":
+            _check_image(j["mask"], f"job {i} mask", torch.uint8, dev)
+            dev = j["mask"].device
+            _check_image(j["marker"], f"job {i} marker", torch.uint8, dev)
+            _check_image(j["out"], f"job {i} out", torch.uint8, dev)
+            if not (j["marker"].shape == j["mask"].shape == j["out"].shape):
+                raise ValueError(f"job {i}: shapes differ")
+            h, w = j["mask"].shape
+            arr[i] = _lib.Job(_lib.IWPP_OP_RECON, conn, h, w, j["marker"].data_ptr(), j["mask"].data_ptr(),
+                              j["out"].data_ptr(), None)
+        elif j["op"] == "edt":
+            _check_image(j["binary"], f"job {i} binary", torch.uint8, dev)
+            dev = j["binary"].device
+            _check_image(j["sqdist"], f"job {i} sqdist", torch.int32, dev)
+            _check_image(j["nearest"], f"job {i} nearest", torch.int32, dev)
+            if not (j["binary"].shape == j["sqdist"].shape == j["nearest"].shape):
+                raise ValueError(f"job {i}: shapes differ")
+            h, w = j["binary"].shape
+            arr[i] = _lib.Job(_lib.IWPP_OP_EDT, conn, h, w, j["binary"].data_ptr(), None,
+                              j["sqdist"].data_ptr(), j["nearest"].data_ptr())
+        else:
+            raise ValueError(f"job {i}: op must be 'recon' or 'edt'")
+    return arr, dev
+
+
+class BatchGraph:
+    """A batch captured into a HIP graph (iwpp_batch_graph_create): one launch
+    replays every kernel of every job on the given (or current) stream."""
+
+    def __init__(self, ctx: Context, handle, device, keep: list):
+        self._lib = ctx._lib
+        self._ctx = ctx
+        self._h = handle
+        self.device = device
+        self._keep = keep  # the tensors the graph reads and writes
+
+    def launch(self, stream=None) -> None:
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rc = self._lib.iwpp_batch_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream))
+        if rc != _lib.IWPP_OK:
+            raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
+
+    def stats(self) -> dict:
+        st = _lib.Stats()
+        rc = self._lib.iwpp_batch_graph_stats(self._h, ctypes.byref(st))
+        if rc != _lib.IWPP_OK:
+            raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
+        return _stats_dict(st)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.iwpp_batch_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_host(t, name: str, dtype):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if t.device.type != "cpu":
+        raise ValueError(f"{name} must be a host (CPU) tensor")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be 2-D and contiguous")
+
+
+class Server:
+    """A request loop on a context (iwpp_server_*): jobs with HOST tensors
+    (pinned memory lets copies overlap compute) are admitted against a device
+    memory budget, run in continuous batches and copied back.  While it runs,
+    the context's other calls raise (busy)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, scratch_bytes: int = 0, max_inflight: int = 0,
+                 max_batch: int = 0):
+        o = _lib.ServerOptions()
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.scratch_bytes = int(scratch_bytes)
+        o.max_inflight = int(max_inflight)
+        o.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        rc = ctx._lib.iwpp_server_start(ctx._h, ctypes.byref(o), ctypes.byref(h))
+        if rc != _lib.IWPP_OK:
+            ctx._err(rc)
+        self._ctx = ctx
+        self._lib = ctx._lib
+        self._h = h
+        self._keep = {}  # ticket -> tensors the job reads or writes
+
+    def _err(self, rc):
+        raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
+
+    def submit(self, job: dict, arrival_ns: int = 0) -> int:
+        """Queue a job: ``{"op": "recon", "marker", "mask", "out", "conn"}`` or
+        ``{"op": "edt", "binary", "sqdist", "nearest", "conn"}`` with CPU
+        tensors; `arrival_ns` on time.monotonic_ns()'s clock (0 = now)."""
+        torch = _torch()
+        conn = int(job.get("conn", 8))
+        if job["op"] == "recon":
+            for k in ("marker", "mask", "out"):
+                _check_host(job[k], k, torch.uint8)
+            if not (job["marker"].shape == job["mask"].shape == job["out"].shape):
+                raise ValueError("shapes differ")
+            h, w = job["mask"].shape
+            j = _lib.Job(_lib.IWPP_OP_RECON, conn, h, w, job["marker"].data_ptr(), job["mask"].data_ptr(),
+                         job["out"].data_ptr(), None)
+            keep = (job["marker"], job["mask"], job["out"])
+        elif job["op"] == "edt":
+            _check_host(job["binary"], "binary", torch.uint8)
+            _check_host(job["sqdist"], "sqdist", torch.int32)
+            _check_host(job["nearest"], "nearest", torch.int32)
+            if not (job["binary"].shape == job["sqdist"].shape == job["nearest"].shape):
+                raise ValueError("shapes differ")
+            h, w = job["binary"].shape
+            j = _lib.Job(_lib.IWPP_OP_EDT, conn, h, w, job["binary"].data_ptr(), None, job["sqdist"].data_ptr(),
+                         job["nearest"].data_ptr())
+            keep = (job["binary"], job["sqdist"], job["nearest"])
+        else:
+            raise ValueError("op must be 'recon' or 'edt'")
+        t = ctypes.c_uint64()
+        rc = self._lib.iwpp_server_submit(self._h, ctypes.byref(j), int(arrival_ns), ctypes.byref(t))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        self._keep[t.value] = keep
+        return t.value
+
+    def poll(self, ticket: int):
+        """(state, latency_ms): state is one of _lib.JOB_*; latency -1 until done."""
+        s = ctypes.c_int32()
+        lat = ctypes.c_double()
+        rc = self._lib.iwpp_server_poll(self._h, int(ticket), ctypes.byref(s), ctypes.byref(lat))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        if s.value in (_lib.JOB_DONE, _lib.JOB_FAILED):
+            self._keep.pop(int(ticket), None)
+        return s.value, lat.value
+
+    def drain(self, timeout_ms: int = -1) -> None:
+        rc = self._lib.iwpp_server_drain(self._h, int(timeout_ms))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        rc = self._lib.iwpp_server_get_stats(self._h, ctypes.byref(st))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return {n: getattr(st, n) for n, _ in _lib.ServerStats._fields_ if n != "reserved"}
+
+    def stop(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            h, self._h = self._h, ctypes.c_void_p()
+            rc = self._lib.iwpp_server_stop(h)
+            self._keep.clear()
+            if rc != _lib.IWPP_OK:
+                self._err(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def _stats_dict(st) -> dict:
+    return {"status": st.status, "op": st.op, "seeds": st.seeds, "items": st.items, "sweeps": st.sweeps,
+            "rounds": st.rounds, "updates": st.updates, "overflow_restarts": st.overflow_restarts}
 
 
 _contexts: dict = {}

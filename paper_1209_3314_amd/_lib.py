@@ -17,6 +17,8 @@ IWPP_EBUSY = -4
 EXPORTED = (
     "iwpp_version", "iwpp_create", "iwpp_destroy", "iwpp_last_error",
     "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats", "iwpp_profile_read", "iwpp_run_batch",
+    "iwpp_set_options", "iwpp_server_start", "iwpp_server_submit", "iwpp_server_poll", "iwpp_server_drain",
+    "iwpp_server_get_stats", "iwpp_server_stop", "iwpp_batch_graph_create", "iwpp_batch_graph_launch", "iwpp_batch_graph_stats", "iwpp_batch_graph_destroy",
 )
 IWPP_OP_RECON = 1
 IWPP_OP_EDT = 2
@@ -30,8 +32,28 @@ class Options(ctypes.Structure):
         ("mr_max_sweeps", ctypes.c_int32),
         ("persistent_blocks", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("mr_seed_sweeps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("scratch_bytes", ctypes.c_int64),
+        ("max_inflight", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "batches", "max_batch_jobs",
+                                              "peak_bytes", "admitted_now", "queued_now")] + [
+        ("reserved", ctypes.c_int64 * 4)]
+
+
+JOB_QUEUED, JOB_ADMITTED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3, 4
 
 
 class Job(ctypes.Structure):
@@ -96,6 +118,28 @@ def load():
     lib.iwpp_get_stats.restype = i32
     lib.iwpp_run_batch.argtypes = [vp, ctypes.POINTER(Job), i32, vp]
     lib.iwpp_run_batch.restype = i32
+    lib.iwpp_server_start.argtypes = [vp, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
+    lib.iwpp_server_start.restype = i32
+    lib.iwpp_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.iwpp_server_submit.restype = i32
+    lib.iwpp_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    lib.iwpp_server_poll.restype = i32
+    lib.iwpp_server_drain.argtypes = [vp, ctypes.c_int64]
+    lib.iwpp_server_drain.restype = i32
+    lib.iwpp_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.iwpp_server_get_stats.restype = i32
+    lib.iwpp_server_stop.argtypes = [vp]
+    lib.iwpp_server_stop.restype = i32
+    lib.iwpp_set_options.argtypes = [vp, ctypes.POINTER(Options)]
+    lib.iwpp_set_options.restype = i32
+    lib.iwpp_batch_graph_create.argtypes = [vp, ctypes.POINTER(Job), i32, ctypes.POINTER(vp)]
+    lib.iwpp_batch_graph_create.restype = i32
+    lib.iwpp_batch_graph_launch.argtypes = [vp, vp]
+    lib.iwpp_batch_graph_launch.restype = i32
+    lib.iwpp_batch_graph_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.iwpp_batch_graph_stats.restype = i32
+    lib.iwpp_batch_graph_destroy.argtypes = [vp]
+    lib.iwpp_batch_graph_destroy.restype = None
     lib.iwpp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
     lib.iwpp_profile_read.restype = i32
     _lib = lib

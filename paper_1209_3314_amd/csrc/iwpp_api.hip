@@ -1,6 +1,13 @@
 // Host side of the C ABI declared in include/iwpp.h: context, argument
-// checks, scratch management and launch sequencing.  No exception or C++ type
-// crosses the ABI; every entry point returns an iwpp_status code.
+// checks, launch plans, scratch management and graph capture.  No exception
+// or C++ type crosses the ABI; every entry point returns an iwpp_status code.
+//
+// A call is turned into a plan: its images grouped by (operation,
+// connectivity), each group with the job table its kernels read.  A group is
+// launched on a scratch area (work lists, flags, EDT feature buffers) and a
+// small fixed area (grid barrier, list counts, statistics).  Eager calls use
+// the context's areas, growing the scratch on demand; a batch graph owns its
+// areas so that its captured launches stay valid.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -12,20 +19,18 @@
 #include "../../include/iwpp.h"
 #include "iwpp_device.hpp"
 #include "iwpp_internal.hpp"
+#include "iwpp_runtime.hpp"
 
-struct iwpp_ctx {
-  int device = 0;
-  iwpp_options opt{};
-  std::string err;
-  // fixed area: barrier | counts | lost | ovf | stats
+static_assert(sizeof(iwpp::GridBarrier) <= iwpp::kBarrierBytes, "barrier area too small");
+
+struct iwpp_graph {
+  iwpp_ctx* ctx = nullptr;
   uint8_t* fixed = nullptr;
-  // growable scratch
   uint8_t* scratch = nullptr;
-  size_t scratch_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   hipStream_t last_stream = nullptr;
-  int last_op = 0;
-  bool have_call = false;
-  iwpp::Recorder rec;
+  bool launched = false;
 };
 
 namespace iwpp {
@@ -79,42 +84,221 @@ void Recorder::release() {
 
 }  // namespace iwpp
 
-namespace {
+namespace iwpp::rt {
 
 thread_local std::string g_create_err;
-
-constexpr size_t kOffBarrier = 0;
-constexpr size_t kOffCounts = kOffBarrier + iwpp::kBarrierBytes;
-constexpr size_t kOffLost = kOffCounts + iwpp::kCountsBytes;
-constexpr size_t kOffOvf = kOffLost + iwpp::kLostBytes;
-constexpr size_t kOffStats = kOffOvf + 256;
-constexpr size_t kFixedBytes = kOffStats + iwpp::kStatsBytes;
-static_assert(sizeof(iwpp::GridBarrier) <= iwpp::kBarrierBytes, "barrier area too small");
-static_assert(kOffStats % 8 == 0, "stats must be 8-byte aligned");
 
 int32_t fail(iwpp_ctx* ctx, int32_t code, const std::string& msg) {
   if (ctx) ctx->err = msg;
   return code;
 }
 
-// Makes `dev` current for the duration of a call and restores the caller's device.
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) return;
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) return;
-    ok = true;
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) return;
+  if (prev != dev && hipSetDevice(dev) != hipSuccess) return;
+  ok = true;
+}
+
+DeviceGuard::~DeviceGuard() {
+  int cur = -1;
+  if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
+
+size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
+  const uint64_t t = op == IWPP_OP_RECON ? (uint64_t)((h + 63) / 64) * (uint64_t)((w + 63) / 64)
+                                         : (uint64_t)((h + 31) / 32) * (uint64_t)((w + 31) / 32);
+  const uint64_t np = (uint64_t)h * (uint64_t)w;
+  // 5 tile words (+ alignment slack of the per-group arrays is added by the caller)
+  return (size_t)(20 * t + (op == IWPP_OP_EDT ? 8 * np : 0) + (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
+}
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
   return x < y + nb && y < x + na;
+}
+
+// ---- plans ---------------------------------------------------------------------
+
+void mr_place(iwpp::MrJob& m, uint64_t& tiles) {
+  m.tiles_y = (m.h + 63) / 64;
+  m.tiles_x = (m.w + 63) / 64;
+  m.tile_base = (uint32_t)tiles;
+  tiles += (uint64_t)m.tiles_y * (uint64_t)m.tiles_x;
+}
+
+void edt_place(iwpp::EdtJob& e, uint64_t& pix, uint64_t& tiles) {
+  e.tiles_y = (e.h + 31) / 32;
+  e.tiles_x = (e.w + 31) / 32;
+  e.tile_base = (uint32_t)tiles;
+  e.pix_base = pix;
+  tiles += (uint64_t)e.tiles_y * (uint64_t)e.tiles_x;
+  pix += (uint64_t)e.h * (uint64_t)e.w;
+}
+
+// Validate the jobs and group them by (op, conn).  `who` prefixes messages.
+int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* who, Plan& plan) {
+  if (!jobs || n < 1) return fail(ctx, IWPP_EINVAL, std::string(who) + ": need at least one job");
+  struct Span {
+    const void* p;
+    size_t n;
+    int job;
+    bool out;
+  };
+  std::vector<Span> spans;
+  for (int32_t i = 0; i < n; ++i) {
+    const iwpp_job& j = jobs[i];
+    const std::string at = std::string(who) + ": job " + std::to_string(i) + ": ";
+    if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_EDT) return fail(ctx, IWPP_EINVAL, at + "op must be RECON or EDT");
+    if (j.conn != 4 && j.conn != 8) return fail(ctx, IWPP_EINVAL, at + "conn must be 4 or 8");
+    if (j.height < 1 || j.width < 1) return fail(ctx, IWPP_EINVAL, at + "height and width must be >= 1");
+    const uint64_t np = (uint64_t)j.height * (uint64_t)j.width;
+    if (j.op == IWPP_OP_RECON) {
+      if (!j.in0 || !j.in1 || !j.out0 || j.out1)
+        return fail(ctx, IWPP_EINVAL, at + "reconstruction needs in0 (marker), in1 (mask), out0 and no out1");
+      if (np > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, at + "image larger than 2^32 - 1 pixels");
+      if (overlaps(j.out0, np, j.in1, np)) return fail(ctx, IWPP_EINVAL, at + "out must not alias mask");
+      if (j.out0 != j.in0 && overlaps(j.out0, np, j.in0, np))
+        return fail(ctx, IWPP_EINVAL, at + "out may equal marker but must not partially overlap it");
+      spans.push_back({j.in1, np, i, false});
+      if (j.out0 != j.in0) spans.push_back({j.in0, np, i, false});
+      spans.push_back({j.out0, np, i, true});
+    } else {
+      if (!j.in0 || j.in1 || !j.out0 || !j.out1)
+        return fail(ctx, IWPP_EINVAL, at + "EDT needs in0 (binary), out0 (sqdist), out1 (nearest) and no in1");
+      if (j.height > 32767 || j.width > 32767) return fail(ctx, IWPP_EINVAL, at + "EDT height and width must be <= 32767");
+      if (overlaps(j.out0, np * 4, j.out1, np * 4) || overlaps(j.out0, np * 4, j.in0, np) ||
+          overlaps(j.out1, np * 4, j.in0, np))
+        return fail(ctx, IWPP_EINVAL, at + "outputs must not alias each other or the input");
+      spans.push_back({j.in0, np, i, false});
+      spans.push_back({j.out0, np * 4, i, true});
+      spans.push_back({j.out1, np * 4, i, true});
+    }
+  }
+  for (size_t a = 0; a < spans.size(); ++a)
+    for (size_t b = a + 1; b < spans.size(); ++b)
+      if (spans[a].job != spans[b].job && (spans[a].out || spans[b].out) &&
+          overlaps(spans[a].p, spans[a].n, spans[b].p, spans[b].n))
+        return fail(ctx, IWPP_EINVAL, std::string(who) + ": an output of job " +
+                                          std::to_string(spans[a].out ? spans[a].job : spans[b].job) +
+                                          " overlaps a buffer of job " +
+                                          std::to_string(spans[a].out ? spans[b].job : spans[a].job));
+  for (int op : {IWPP_OP_RECON, IWPP_OP_EDT}) {
+    for (int conn : {8, 4}) {
+      Group g;
+      g.op = op;
+      g.conn = conn;
+      for (int32_t i = 0; i < n; ++i) {
+        const iwpp_job& j = jobs[i];
+        if (j.op != op || j.conn != conn) continue;
+        if (op == IWPP_OP_RECON) {
+          iwpp::MrJob m{};
+          m.marker = j.in0;
+          m.mask = j.in1;
+          m.out = static_cast<uint8_t*>(j.out0);
+          m.h = j.height;
+          m.w = j.width;
+          mr_place(m, g.ntiles);
+          g.mr.push_back(m);
+        } else {
+          iwpp::EdtJob e{};
+          e.bin = j.in0;
+          e.sqdist = static_cast<int32_t*>(j.out0);
+          e.nearest = static_cast<int32_t*>(j.out1);
+          e.h = j.height;
+          e.w = j.width;
+          edt_place(e, g.npix, g.ntiles);
+          g.edt.push_back(e);
+        }
+      }
+      if (g.njobs() == 0) continue;
+      if (g.ntiles >= 0x7FFFFFFFull) return fail(ctx, IWPP_EINVAL, std::string(who) + ": too many tiles in one group");
+      g.table_off = plan.table_bytes;
+      plan.table_bytes += g.table_bytes();
+      if (g.scratch_bytes() > plan.scratch_bytes) plan.scratch_bytes = g.scratch_bytes();
+      plan.groups.push_back(std::move(g));
+    }
+  }
+  return IWPP_OK;
+}
+
+int32_t upload_tables(iwpp_ctx* ctx, const Plan& plan, uint8_t* tables, hipStream_t st, bool sync) {
+  for (const Group& g : plan.groups) {
+    if (g.njobs() <= 1) continue;
+    const void* src = g.op == IWPP_OP_RECON ? (const void*)g.mr.data() : (const void*)g.edt.data();
+    const size_t bytes = g.op == IWPP_OP_RECON ? g.mr.size() * sizeof(iwpp::MrJob) : g.edt.size() * sizeof(iwpp::EdtJob);
+    const hipError_t e = sync ? hipMemcpy(tables + g.table_off, src, bytes, hipMemcpyHostToDevice)
+                              : hipMemcpyAsync(tables + g.table_off, src, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, IWPP_EDEVICE, "job table upload failed");
+    }
+  }
+  return IWPP_OK;
+}
+
+void pack_tables(const Plan& plan, uint8_t* host) {
+  for (const Group& g : plan.groups) {
+    if (g.njobs() <= 1) continue;
+    const void* src = g.op == IWPP_OP_RECON ? (const void*)g.mr.data() : (const void*)g.edt.data();
+    const size_t bytes = g.op == IWPP_OP_RECON ? g.mr.size() * sizeof(iwpp::MrJob) : g.edt.size() * sizeof(iwpp::EdtJob);
+    std::memcpy(host + g.table_off, src, bytes);
+  }
+}
+
+// Launch the kernels of one group on `st`, using `scratch`/`fixed`/`tables`.
+// `first` also clears the statistics.
+int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* fixed, uint8_t* tables, hipStream_t st,
+                     bool first, iwpp::Recorder* rec) {
+  rec->begin(IWPP_K_RESET, st);
+  const int zr = iwpp::zero_words(reinterpret_cast<uint32_t*>(fixed), (first ? kFixedBytes : kOffStats) / 4, st);
+  rec->end(st);
+  if (zr != 0) return fail(ctx, IWPP_EDEVICE, "reset kernel launch failed");
+  const size_t tb = align256(g.ntiles * 4);
+  const uint32_t nj = g.njobs();
+  const char* e = "";
+  int lr = 0;
+  if (g.op == IWPP_OP_RECON) {
+    iwpp::MrArgs a{};
+    a.job0 = g.mr[0];
+    a.njobs = nj;
+    a.ntiles = (uint32_t)g.ntiles;
+    const int64_t cap = ctx->opt.mr_list_capacity;
+    a.list_cap = (cap > 0 && (uint64_t)cap < g.ntiles) ? (uint32_t)cap : (uint32_t)g.ntiles;
+    a.max_sweeps = ctx->opt.mr_max_sweeps > 0 ? ctx->opt.mr_max_sweeps : 64;
+    a.seed_sweeps = ctx->opt.mr_seed_sweeps > 0 ? ctx->opt.mr_seed_sweeps : 64;
+    a.flags = reinterpret_cast<uint32_t*>(scratch);
+    a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * tb);
+    a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 4 * tb) : nullptr;
+    a.jobs = nj > 1 ? reinterpret_cast<const iwpp::MrJob*>(tables + g.table_off) : nullptr;
+    a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
+    a.lost = reinterpret_cast<uint32_t*>(fixed + kOffLost);
+    a.bar = reinterpret_cast<iwpp::GridBarrier*>(fixed + kOffBarrier);
+    a.stats = reinterpret_cast<unsigned long long*>(fixed + kOffStats);
+    lr = iwpp::mr_launch(a, g.conn, ctx->opt.persistent_blocks, st, rec, &e);
+  } else {
+    iwpp::EdtArgs a{};
+    const size_t fb = align256(g.npix * 4);
+    a.job0 = g.edt[0];
+    a.njobs = nj;
+    a.npix = g.npix;
+    a.ntiles = (uint32_t)g.ntiles;
+    a.feat0 = reinterpret_cast<uint32_t*>(scratch);
+    a.feat1 = reinterpret_cast<uint32_t*>(scratch + fb);
+    a.flags = reinterpret_cast<uint32_t*>(scratch + 2 * fb);
+    a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * fb + 2 * tb);
+    a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 2 * fb + 4 * tb) : nullptr;
+    a.jobs = nj > 1 ? reinterpret_cast<const iwpp::EdtJob*>(tables + g.table_off) : nullptr;
+    a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
+    a.ovf = reinterpret_cast<uint32_t*>(fixed + kOffOvf);
+    a.bar = reinterpret_cast<iwpp::GridBarrier*>(fixed + kOffBarrier);
+    a.stats = reinterpret_cast<unsigned long long*>(fixed + kOffStats);
+    lr = iwpp::edt_launch(a, g.conn, ctx->opt.persistent_blocks, st, rec, &e);
+  }
+  if (lr != 0) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, std::string(g.op == IWPP_OP_RECON ? "morph_recon: " : "edt: ") + e);
+  }
+  return IWPP_OK;
 }
 
 int32_t ensure_scratch(iwpp_ctx* ctx, size_t bytes) {
@@ -137,119 +321,67 @@ int32_t ensure_scratch(iwpp_ctx* ctx, size_t bytes) {
   return IWPP_OK;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// Clear list fill levels, lost flags and the barrier before a launch group,
-// and the statistics too at the start of a call.
-int32_t reset_fixed(iwpp_ctx* ctx, hipStream_t stream, bool stats) {
-  ctx->rec.begin(IWPP_K_RESET, stream);
-  const int r = iwpp::zero_words(reinterpret_cast<uint32_t*>(ctx->fixed), (stats ? kFixedBytes : kOffStats) / 4, stream);
-  ctx->rec.end(stream);
-  if (r != 0) return fail(ctx, IWPP_EDEVICE, "reset kernel launch failed");
-  return IWPP_OK;
-}
-
-void bind_fixed_mr(iwpp_ctx* ctx, iwpp::MrArgs& a) {
-  a.counts = reinterpret_cast<uint32_t*>(ctx->fixed + kOffCounts);
-  a.lost = reinterpret_cast<uint32_t*>(ctx->fixed + kOffLost);
-  a.bar = reinterpret_cast<iwpp::GridBarrier*>(ctx->fixed + kOffBarrier);
-  a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
-}
-
-void bind_fixed_edt(iwpp_ctx* ctx, iwpp::EdtArgs& a) {
-  a.counts = reinterpret_cast<uint32_t*>(ctx->fixed + kOffCounts);
-  a.ovf = reinterpret_cast<uint32_t*>(ctx->fixed + kOffOvf);
-  a.bar = reinterpret_cast<iwpp::GridBarrier*>(ctx->fixed + kOffBarrier);
-  a.stats = reinterpret_cast<unsigned long long*>(ctx->fixed + kOffStats);
-}
-
-// Scratch bytes of one reconstruction launch over `ntiles` tiles / `njobs` images.
-size_t mr_scratch_bytes(uint64_t ntiles, uint32_t njobs) {
-  return 5 * align256(ntiles * 4) + align256((size_t)njobs * sizeof(iwpp::MrJob));
-}
-
-// Scratch bytes of one distance-transform launch over `npix` pixels / `njobs` images.
-size_t edt_scratch_bytes(uint64_t npix, uint32_t njobs) {
-  return 4 * align256(npix * 8) + align256(npix * 4) + align256((size_t)njobs * sizeof(iwpp::EdtJob));
-}
-
-// Launch one reconstruction group (jobs already validated; tile_base filled).
-int32_t run_mr(iwpp_ctx* ctx, const std::vector<iwpp::MrJob>& jobs, uint32_t ntiles, int conn, hipStream_t st,
-               bool first) {
-  iwpp::MrArgs a{};
-  const uint32_t nj = (uint32_t)jobs.size();
-  a.job0 = jobs[0];
-  a.njobs = nj;
-  a.ntiles = ntiles;
-  const int64_t cap = ctx->opt.mr_list_capacity;
-  a.list_cap = (cap > 0 && (uint64_t)cap < ntiles) ? (uint32_t)cap : ntiles;
-  a.max_sweeps = ctx->opt.mr_max_sweeps > 0 ? ctx->opt.mr_max_sweeps : 64;
-  a.seed_sweeps = a.max_sweeps;
-  const size_t tb = align256((size_t)ntiles * 4);
-  int32_t rc = ensure_scratch(ctx, mr_scratch_bytes(ntiles, nj));
+// Run a plan eagerly on the context's areas.
+int32_t run_plan(iwpp_ctx* ctx, const Plan& plan, hipStream_t st, int op_code) {
+  const size_t sb = align256(plan.scratch_bytes);
+  int32_t rc = ensure_scratch(ctx, sb + plan.table_bytes);
   if (rc != IWPP_OK) return rc;
-  // layout: flags[2][T] | lists[2][T] | tile_job[T] | job table
-  a.flags = reinterpret_cast<uint32_t*>(ctx->scratch);
-  a.lists = reinterpret_cast<uint32_t*>(ctx->scratch + 2 * tb);
-  a.tile_job = nullptr;
-  a.jobs = nullptr;
-  if (nj > 1) {
-    iwpp::MrJob* dj = reinterpret_cast<iwpp::MrJob*>(ctx->scratch + 5 * tb);
-    a.tile_job = reinterpret_cast<uint32_t*>(ctx->scratch + 4 * tb);
-    a.jobs = dj;
-    if (hipMemcpyAsync(dj, jobs.data(), nj * sizeof(iwpp::MrJob), hipMemcpyHostToDevice, st) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ctx, IWPP_EDEVICE, "job table upload failed");
-    }
+  uint8_t* tables = ctx->scratch + sb;
+  if ((rc = upload_tables(ctx, plan, tables, st, false)) != IWPP_OK) return rc;
+  bool first = true;
+  for (const Group& g : plan.groups) {
+    if ((rc = launch_group(ctx, g, ctx->scratch, ctx->fixed, tables, st, first, &ctx->rec)) != IWPP_OK) return rc;
+    first = false;
   }
-  bind_fixed_mr(ctx, a);
-  if ((rc = reset_fixed(ctx, st, first)) != IWPP_OK) return rc;
-  const char* e = "";
-  if (iwpp::mr_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, std::string("morph_recon: ") + e);
-  }
+  ctx->last_stream = st;
+  ctx->last_op = op_code;
+  ctx->have_call = true;
   return IWPP_OK;
 }
 
-int32_t run_edt(iwpp_ctx* ctx, const std::vector<iwpp::EdtJob>& jobs, uint64_t npix, int conn, hipStream_t st,
-                bool first) {
-  iwpp::EdtArgs a{};
-  const uint32_t nj = (uint32_t)jobs.size();
-  a.job0 = jobs[0];
-  a.njobs = nj;
-  a.npix = (uint32_t)npix;
-  const size_t kb = align256((size_t)npix * 8);
-  int32_t rc = ensure_scratch(ctx, edt_scratch_bytes(npix, nj));
-  if (rc != IWPP_OK) return rc;
-  a.key0 = reinterpret_cast<unsigned long long*>(ctx->scratch);
-  a.key1 = reinterpret_cast<unsigned long long*>(ctx->scratch + kb);
-  a.lists = reinterpret_cast<unsigned long long*>(ctx->scratch + 2 * kb);
-  a.stamp = reinterpret_cast<uint32_t*>(ctx->scratch + 4 * kb);
-  a.jobs = nullptr;
-  if (nj > 1) {
-    iwpp::EdtJob* dj = reinterpret_cast<iwpp::EdtJob*>(ctx->scratch + 4 * kb + align256((size_t)npix * 4));
-    a.jobs = dj;
-    if (hipMemcpyAsync(dj, jobs.data(), nj * sizeof(iwpp::EdtJob), hipMemcpyHostToDevice, st) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ctx, IWPP_EDEVICE, "job table upload failed");
-    }
-  }
-  bind_fixed_edt(ctx, a);
-  if ((rc = reset_fixed(ctx, st, first)) != IWPP_OK) return rc;
-  const char* e = "";
-  if (iwpp::edt_launch(a, conn, ctx->opt.persistent_blocks, st, &ctx->rec, &e) != 0) {
+int32_t read_stats(iwpp_ctx* ctx, const uint8_t* fixed, hipStream_t st, int op, iwpp_stats* out) {
+  std::memset(out, 0, sizeof(*out));
+  if (hipStreamSynchronize(st) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, std::string("edt: ") + e);
+    return fail(ctx, IWPP_EDEVICE, "get_stats: the last call's stream reported an error");
   }
+  unsigned long long h[iwpp::kStatShards * iwpp::kStatFields];
+  if (hipMemcpy(h, fixed + kOffStats, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, "get_stats: copy failed");
+  }
+  fold_stats(h, op, out);
+  if (out->status != IWPP_OK) ctx->err = "a kernel hit its safety limit (grid barrier timeout or round cap)";
   return IWPP_OK;
 }
 
-}  // namespace
+void fold_stats(const unsigned long long* h, int op, iwpp_stats* out) {
+  std::memset(out, 0, sizeof(*out));
+  unsigned long long f[iwpp::kStatFields] = {};
+  for (int s = 0; s < iwpp::kStatShards; ++s)
+    for (int k = 0; k < iwpp::kStatFields; ++k) f[k] += h[s * iwpp::kStatFields + k];
+  out->op = op;
+  out->seeds = (int64_t)f[iwpp::kStatSeeds];
+  out->items = (int64_t)f[iwpp::kStatItems];
+  out->sweeps = (int64_t)f[iwpp::kStatSweeps];
+  out->rounds = (int64_t)f[iwpp::kStatRounds];
+  out->updates = (int64_t)f[iwpp::kStatUpdates];
+  out->overflow_restarts = (int64_t)f[iwpp::kStatRestarts];
+  out->status = f[iwpp::kStatError] ? IWPP_EDEVICE : IWPP_OK;
+}
+
+bool options_valid(const iwpp_options& o) {
+  return o.mr_list_capacity >= 0 && o.mr_max_sweeps >= 0 && o.persistent_blocks >= 0 && o.profile >= 0 &&
+         o.mr_seed_sweeps >= 0;
+}
+
+}  // namespace iwpp::rt
+
+using namespace iwpp::rt;
 
 extern "C" {
 
-int32_t iwpp_version(void) { return (0 << 16) | 1; }
+int32_t iwpp_version(void) { return (0 << 16) | 3; }
 
 int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out) {
   if (!out) {
@@ -269,6 +401,11 @@ int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out) {
     return IWPP_ENOMEM;
   }
   ctx->device = device;
+  if (opt && !options_valid(*opt)) {
+    delete ctx;
+    g_create_err = "iwpp_create: negative option value";
+    return IWPP_EINVAL;
+  }
   if (opt) ctx->opt = *opt;
   ctx->rec.enabled = ctx->opt.profile != 0;
   DeviceGuard g(device);
@@ -292,6 +429,7 @@ int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out) {
 
 void iwpp_destroy(iwpp_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->server) (void)iwpp_server_stop(ctx->server);
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
@@ -310,158 +448,147 @@ const char* iwpp_last_error(const iwpp_ctx* ctx) {
 int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out, int32_t height,
                             int32_t width, int32_t conn, void* stream) {
   if (!ctx) return IWPP_EINVAL;
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "morph_recon: the context is serving");
   if (!marker || !mask || !out) return fail(ctx, IWPP_EINVAL, "morph_recon: NULL image pointer");
-  if (height < 1 || width < 1) return fail(ctx, IWPP_EINVAL, "morph_recon: height and width must be >= 1");
-  if (conn != 4 && conn != 8) return fail(ctx, IWPP_EINVAL, "morph_recon: conn must be 4 or 8");
-  const uint64_t npix = (uint64_t)height * (uint64_t)width;
-  if (npix > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, "morph_recon: image larger than 2^32 - 1 pixels");
-  if (overlaps(out, npix, mask, npix)) return fail(ctx, IWPP_EINVAL, "morph_recon: out must not alias mask");
-  if (out != marker && overlaps(out, npix, marker, npix))
-    return fail(ctx, IWPP_EINVAL, "morph_recon: out may equal marker but must not partially overlap it");
+  iwpp_job j{IWPP_OP_RECON, conn, height, width, marker, mask, out, nullptr};
+  Plan plan;
+  int32_t rc = build_plan(ctx, &j, 1, "morph_recon", plan);
+  if (rc != IWPP_OK) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "morph_recon: cannot select the context's device");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-
-  iwpp::MrJob job{};
-  job.marker = marker;
-  job.mask = mask;
-  job.out = out;
-  job.h = height;
-  job.w = width;
-  job.tiles_y = (height + 63) / 64;
-  job.tiles_x = (width + 63) / 64;
-  job.tile_base = 0;
-  const uint32_t ntiles = (uint32_t)job.tiles_y * (uint32_t)job.tiles_x;
-  const int32_t rc = run_mr(ctx, std::vector<iwpp::MrJob>{job}, ntiles, conn, st, true);
-  if (rc != IWPP_OK) return rc;
-  ctx->last_stream = st;
-  ctx->last_op = 1;
-  ctx->have_call = true;
-  return IWPP_OK;
+  return run_plan(ctx, plan, static_cast<hipStream_t>(stream), 1);
 }
 
 int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
                  int32_t width, int32_t conn, void* stream) {
   if (!ctx) return IWPP_EINVAL;
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "edt: the context is serving");
   if (!binary || !sqdist || !nearest) return fail(ctx, IWPP_EINVAL, "edt: NULL image pointer");
-  if (height < 1 || width < 1 || height > 32767 || width > 32767)
-    return fail(ctx, IWPP_EINVAL, "edt: height and width must be in [1, 32767]");
-  if (conn != 4 && conn != 8) return fail(ctx, IWPP_EINVAL, "edt: conn must be 4 or 8");
-  const uint64_t npix = (uint64_t)height * (uint64_t)width;
-  if (overlaps(sqdist, npix * 4, nearest, npix * 4) || overlaps(sqdist, npix * 4, binary, npix) ||
-      overlaps(nearest, npix * 4, binary, npix))
-    return fail(ctx, IWPP_EINVAL, "edt: outputs must not alias each other or the input");
+  iwpp_job j{IWPP_OP_EDT, conn, height, width, binary, nullptr, sqdist, nearest};
+  Plan plan;
+  int32_t rc = build_plan(ctx, &j, 1, "edt", plan);
+  if (rc != IWPP_OK) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "edt: cannot select the context's device");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-
-  iwpp::EdtJob job{};
-  job.bin = binary;
-  job.sqdist = sqdist;
-  job.nearest = nearest;
-  job.h = height;
-  job.w = width;
-  job.pix_base = 0;
-  const int32_t rc = run_edt(ctx, std::vector<iwpp::EdtJob>{job}, npix, conn, st, true);
-  if (rc != IWPP_OK) return rc;
-  ctx->last_stream = st;
-  ctx->last_op = 2;
-  ctx->have_call = true;
-  return IWPP_OK;
+  return run_plan(ctx, plan, static_cast<hipStream_t>(stream), 2);
 }
 
 int32_t iwpp_run_batch(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, void* stream) {
   if (!ctx) return IWPP_EINVAL;
-  if (!jobs || n < 1) return fail(ctx, IWPP_EINVAL, "run_batch: need at least one job");
-  struct Span {
-    const void* p;
-    size_t n;
-    int job;
-    bool out;
-  };
-  std::vector<Span> spans;
-  for (int32_t i = 0; i < n; ++i) {
-    const iwpp_job& j = jobs[i];
-    const std::string at = "run_batch: job " + std::to_string(i) + ": ";
-    if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_EDT) return fail(ctx, IWPP_EINVAL, at + "op must be RECON or EDT");
-    if (j.conn != 4 && j.conn != 8) return fail(ctx, IWPP_EINVAL, at + "conn must be 4 or 8");
-    if (j.height < 1 || j.width < 1) return fail(ctx, IWPP_EINVAL, at + "height and width must be >= 1");
-    const uint64_t np = (uint64_t)j.height * (uint64_t)j.width;
-    if (j.op == IWPP_OP_RECON) {
-      if (!j.in0 || !j.in1 || !j.out0 || j.out1) return fail(ctx, IWPP_EINVAL, at + "recon needs in0, in1, out0 and no out1");
-      if (np > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, at + "image larger than 2^32 - 1 pixels");
-      spans.push_back({j.in1, np, i, false});
-      if (j.out0 != j.in0) spans.push_back({j.in0, np, i, false});
-      spans.push_back({j.out0, np, i, true});
-    } else {
-      if (!j.in0 || j.in1 || !j.out0 || !j.out1) return fail(ctx, IWPP_EINVAL, at + "EDT needs in0, out0, out1 and no in1");
-      if (j.height > 32767 || j.width > 32767) return fail(ctx, IWPP_EINVAL, at + "EDT sides must be <= 32767");
-      spans.push_back({j.in0, np, i, false});
-      spans.push_back({j.out0, np * 4, i, true});
-      spans.push_back({j.out1, np * 4, i, true});
-    }
-  }
-  for (size_t a = 0; a < spans.size(); ++a)
-    for (size_t b = a + 1; b < spans.size(); ++b)
-      if ((spans[a].out || spans[b].out) && overlaps(spans[a].p, spans[a].n, spans[b].p, spans[b].n))
-        return fail(ctx, IWPP_EINVAL, "run_batch: an output of job " + std::to_string(spans[a].out ? spans[a].job : spans[b].job) +
-                                          " overlaps a buffer of job " + std::to_string(spans[a].out ? spans[b].job : spans[a].job));
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "run_batch: the context is serving");
+  Plan plan;
+  int32_t rc = build_plan(ctx, jobs, n, "run_batch", plan);
+  if (rc != IWPP_OK) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "run_batch: cannot select the context's device");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  bool first = true;
-  for (int op : {IWPP_OP_RECON, IWPP_OP_EDT}) {
-    for (int conn : {8, 4}) {
-      if (op == IWPP_OP_RECON) {
-        std::vector<iwpp::MrJob> group;
-        uint64_t tiles = 0;
-        for (int32_t i = 0; i < n; ++i) {
-          const iwpp_job& j = jobs[i];
-          if (j.op != op || j.conn != conn) continue;
-          iwpp::MrJob m{};
-          m.marker = j.in0;
-          m.mask = j.in1;
-          m.out = static_cast<uint8_t*>(j.out0);
-          m.h = j.height;
-          m.w = j.width;
-          m.tiles_y = (j.height + 63) / 64;
-          m.tiles_x = (j.width + 63) / 64;
-          m.tile_base = (uint32_t)tiles;
-          tiles += (uint64_t)m.tiles_y * (uint64_t)m.tiles_x;
-          group.push_back(m);
-        }
-        if (group.empty()) continue;
-        if (tiles >= 0x7FFFFFFFull) return fail(ctx, IWPP_EINVAL, "run_batch: too many reconstruction tiles");
-        const int32_t rc = run_mr(ctx, group, (uint32_t)tiles, conn, st, first);
-        if (rc != IWPP_OK) return rc;
-      } else {
-        std::vector<iwpp::EdtJob> group;
-        uint64_t pix = 0;
-        for (int32_t i = 0; i < n; ++i) {
-          const iwpp_job& j = jobs[i];
-          if (j.op != op || j.conn != conn) continue;
-          iwpp::EdtJob e{};
-          e.bin = j.in0;
-          e.sqdist = static_cast<int32_t*>(j.out0);
-          e.nearest = static_cast<int32_t*>(j.out1);
-          e.h = j.height;
-          e.w = j.width;
-          e.pix_base = (uint32_t)pix;
-          pix += (uint64_t)j.height * (uint64_t)j.width;
-          group.push_back(e);
-          if (pix > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, "run_batch: EDT group larger than 2^32 - 1 pixels");
-        }
-        if (group.empty()) continue;
-        const int32_t rc = run_edt(ctx, group, pix, conn, st, first);
-        if (rc != IWPP_OK) return rc;
-      }
+  return run_plan(ctx, plan, static_cast<hipStream_t>(stream), 3);
+}
+
+int32_t iwpp_set_options(iwpp_ctx* ctx, const iwpp_options* opt) {
+  if (!ctx) return IWPP_EINVAL;
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "set_options: the context is serving");
+  if (!opt) return fail(ctx, IWPP_EINVAL, "set_options: NULL options");
+  if (!options_valid(*opt)) return fail(ctx, IWPP_EINVAL, "set_options: negative option value");
+  ctx->opt = *opt;
+  ctx->rec.enabled = ctx->opt.profile != 0;
+  return IWPP_OK;
+}
+
+int32_t iwpp_batch_graph_create(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, iwpp_graph** out) {
+  if (!ctx) return IWPP_EINVAL;
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "batch_graph_create: the context is serving");
+  if (!out) return fail(ctx, IWPP_EINVAL, "batch_graph_create: out is NULL");
+  *out = nullptr;
+  Plan plan;
+  int32_t rc = build_plan(ctx, jobs, n, "batch_graph_create", plan);
+  if (rc != IWPP_OK) return rc;
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, IWPP_EDEVICE, "batch_graph_create: cannot select the context's device");
+  iwpp_graph* g = new (std::nothrow) iwpp_graph();
+  if (!g) return fail(ctx, IWPP_ENOMEM, "batch_graph_create: out of host memory");
+  g->ctx = ctx;
+  const size_t sb = align256(plan.scratch_bytes);
+  void* p = nullptr;
+  void* f = nullptr;
+  if (hipMalloc(&p, sb + plan.table_bytes + 256) != hipSuccess || hipMalloc(&f, kFixedBytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (p) (void)hipFree(p);
+    delete g;
+    return fail(ctx, IWPP_ENOMEM, "batch_graph_create: device allocation failed");
+  }
+  g->scratch = static_cast<uint8_t*>(p);
+  g->fixed = static_cast<uint8_t*>(f);
+  hipStream_t cs = nullptr;
+  iwpp::Recorder off;  // no event records inside a graph
+  ctx->err.clear();
+  rc = upload_tables(ctx, plan, g->scratch + sb, nullptr, true);
+  if (rc == IWPP_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(ctx, IWPP_EDEVICE, "batch_graph_create: stream creation failed");
+  if (rc == IWPP_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    rc = fail(ctx, IWPP_EDEVICE, "batch_graph_create: capture could not start");
+  if (rc == IWPP_OK) {
+    bool first = true;
+    for (const Group& grp : plan.groups) {
+      rc = launch_group(ctx, grp, g->scratch, g->fixed, g->scratch + sb, cs, first, &off);
+      if (rc != IWPP_OK) break;
       first = false;
     }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc == IWPP_OK && (ec != hipSuccess || !graph)) rc = fail(ctx, IWPP_EDEVICE, "batch_graph_create: capture failed");
+    g->graph = graph;
   }
-  ctx->last_stream = st;
-  ctx->last_op = 3;
-  ctx->have_call = true;
+  if (rc == IWPP_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = fail(ctx, IWPP_EDEVICE, "batch_graph_create: instantiation failed");
+  if (cs) (void)hipStreamDestroy(cs);
+  if (rc != IWPP_OK) {
+    (void)hipGetLastError();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipFree(g->scratch);
+    (void)hipFree(g->fixed);
+    delete g;
+    if (ctx->err.empty()) ctx->err = "batch_graph_create: device error";
+    return rc == IWPP_EINVAL ? rc : IWPP_EDEVICE;
+  }
+  *out = g;
   return IWPP_OK;
+}
+
+int32_t iwpp_batch_graph_launch(iwpp_graph* g, void* stream) {
+  if (!g) return IWPP_EINVAL;
+  DeviceGuard dg(g->ctx->device);
+  if (!dg.ok) return fail(g->ctx, IWPP_EDEVICE, "batch_graph_launch: cannot select the context's device");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipGraphLaunch(g->exec, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(g->ctx, IWPP_EDEVICE, "batch_graph_launch: launch failed");
+  }
+  g->last_stream = st;
+  g->launched = true;
+  return IWPP_OK;
+}
+
+int32_t iwpp_batch_graph_stats(iwpp_graph* g, iwpp_stats* out) {
+  if (!g || !out) return g ? fail(g->ctx, IWPP_EINVAL, "batch_graph_stats: out is NULL") : IWPP_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  if (!g->launched) return IWPP_OK;
+  DeviceGuard dg(g->ctx->device);
+  if (!dg.ok) return fail(g->ctx, IWPP_EDEVICE, "batch_graph_stats: cannot select the context's device");
+  return read_stats(g->ctx, g->fixed, g->last_stream, 3, out);
+}
+
+void iwpp_batch_graph_destroy(iwpp_graph* g) {
+  if (!g) return;
+  {
+    DeviceGuard dg(g->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->scratch) (void)hipFree(g->scratch);
+    if (g->fixed) (void)hipFree(g->fixed);
+  }
+  delete g;
 }
 
 int32_t iwpp_profile_read(iwpp_ctx* ctx, iwpp_kernel_time* out, int32_t max, int32_t* n) {
@@ -487,28 +614,7 @@ int32_t iwpp_get_stats(iwpp_ctx* ctx, iwpp_stats* out) {
   if (!ctx->have_call) return IWPP_OK;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "get_stats: cannot select the context's device");
-  if (hipStreamSynchronize(ctx->last_stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, "get_stats: the last call's stream reported an error");
-  }
-  unsigned long long h[iwpp::kStatShards * iwpp::kStatFields];
-  if (hipMemcpy(h, ctx->fixed + kOffStats, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, "get_stats: copy failed");
-  }
-  unsigned long long f[iwpp::kStatFields] = {};
-  for (int s = 0; s < iwpp::kStatShards; ++s)
-    for (int k = 0; k < iwpp::kStatFields; ++k) f[k] += h[s * iwpp::kStatFields + k];
-  out->op = ctx->last_op;
-  out->seeds = (int64_t)f[iwpp::kStatSeeds];
-  out->items = (int64_t)f[iwpp::kStatItems];
-  out->sweeps = (int64_t)f[iwpp::kStatSweeps];
-  out->rounds = (int64_t)f[iwpp::kStatRounds];
-  out->updates = (int64_t)f[iwpp::kStatUpdates];
-  out->overflow_restarts = (int64_t)f[iwpp::kStatRestarts];
-  out->status = f[iwpp::kStatError] ? IWPP_EDEVICE : IWPP_OK;
-  if (out->status != IWPP_OK) ctx->err = "a kernel hit its safety limit (grid barrier timeout)";
-  return IWPP_OK;
+  return read_stats(ctx, ctx->fixed, ctx->last_stream, ctx->last_op, out);
 }
 
 }  // extern "C"

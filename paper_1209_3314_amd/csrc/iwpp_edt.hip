@@ -2,115 +2,262 @@
 //
 // What is computed (Sec. 2.2, Algorithms 3 and 6): every pixel carries a
 // nearest feature (the paper's VR), initially itself for features (0-pixels)
-// and "none" otherwise; features are propagated to neighbours in N_G when they
-// are closer; the output is the squared distance to the carried feature and
-// its index.  The propagation runs in level-synchronous rounds -- Algorithm 4's
+// and "none" otherwise; features propagate to neighbours in N_G when they are
+// closer; the output is the squared distance to the carried feature and its
+// index.  The propagation runs in level-synchronous rounds -- Algorithm 4's
 // swap of input and output queues, made device-wide -- and a pixel offers the
-// feature it held at the end of the previous round.  Round r therefore equals
-// the dense operator key_r(q) = min over p in N_G[q] of (d2(q, f_{r-1}(p)),
-// f_{r-1}(p)), so the result does not depend on thread order.
+// feature it held at the end of the previous round, so round r is the dense
+// operator
+//     f_r(q) = argmin over p in N_G[q] of (d2(q, f_{r-1}(p)), f_{r-1}(p))
+// (lexicographic: squared distance, then feature index) and the result does
+// not depend on thread order.
 //
-// State.  A pixel's key is the 64-bit word (d2 << 32) | (fy << 16) | fx;
-// unsigned comparison orders keys by squared distance, then by feature row,
-// then column -- i.e. by (d2, feature index) -- and the CAS-retry loop of
-// Algorithm 6 becomes one 64-bit atomic min.  Two key buffers alternate per
-// round: round r reads buffer (r-1)&1, which no one writes during the round,
-// and lowers buffer r&1 with atomic min.  Buffer r&1 holds the state of round
-// r-2; a pixel that changed in round r-1 is brought up to date by its own
-// frontier item with one more atomic min, and min makes the order of that
-// catch-up and the offers irrelevant.
+// How.  The image is cut into 32x32 tiles.  A round visits only the tiles
+// whose pixels or one-pixel halo changed in the previous round: one wave loads
+// the tile and its halo from the previous round's buffer into LDS, recomputes
+// every pixel of the tile with the operator above, writes the tile to the other
+// buffer, and lists itself and the neighbouring tiles its changes can reach for
+// the next round.  Nothing writes the buffer a round reads, so no atomics touch
+// pixels.  A tile that is not visited in a round keeps equal values in both
+// buffers: a tile changes only in rounds it is visited, and after a round in
+// which it changed it is visited again, so it stops being visited only after a
+// round in which it (re)wrote its unchanged values.
 //
-// Frontier.  A pixel joins the next round's frontier the first time an offer
-// improves it in a round (a round stamp, updated with atomic max, makes the
-// frontier a set).  Items are staged per wave in LDS and flushed with one
-// atomic per batch.  Rounds are separated by a grid barrier.
+// State is the feature's packed coordinates (y << 16 | x), 4 bytes per pixel;
+// squared distances are recomputed exactly in integers.
 #include "iwpp_device.hpp"
 #include "iwpp_internal.hpp"
 
 namespace iwpp {
 namespace edt {
 
+constexpr int TE = 32;            // tile side
+constexpr int RP = TE + 2;        // region side with the halo
 constexpr int kWavesPerBlock = 4;
-constexpr int kStageCap = 1024;
-constexpr unsigned long long kNone = ~0ull;
+constexpr int kStageCap = 128;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kMaxRounds = 1u << 20;
+
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t pack_yx(int y, int x) { return ((uint32_t)y << 16) | (uint32_t)x; }
 
-// Neighbour k of N_G (raster order; 4-connectivity uses the 4 axis neighbours).
-template <int CONN>
-__device__ __forceinline__ void nb_off(int k, int& dy, int& dx) {
-  if (CONN == 8) {
-    dy = k < 3 ? -1 : (k < 5 ? 0 : 1);
-    dx = (k == 0 || k == 3 || k == 5) ? -1 : ((k == 1 || k == 6) ? 0 : 1);
-  } else {
-    dy = k == 0 ? -1 : (k == 3 ? 1 : 0);
-    dx = k == 1 ? -1 : (k == 2 ? 1 : 0);
-  }
+struct TileRef {
+  EdtJob j;
+  int ty, tx;
+};
+
+__device__ __forceinline__ TileRef tile_ref(const EdtArgs& a, uint32_t t) {
+  TileRef r;
+  r.j = a.njobs == 1u ? a.job0 : a.jobs[a.tile_job[t]];
+  const uint32_t lt = t - r.j.tile_base;
+  r.ty = (int)(lt / (uint32_t)r.j.tiles_x);
+  r.tx = (int)(lt - (uint32_t)r.ty * (uint32_t)r.j.tiles_x);
+  return r;
 }
 
-__device__ __forceinline__ unsigned long long make_item(uint32_t job, int y, int x) {
-  return ((unsigned long long)job << 32) | pack_yx(y, x);
+// Buffer resource over the image rows [row0, row0 + rows) of a per-pixel u32 array.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const uint32_t* base, const EdtJob& j, int row0, int rows) {
+  return make_rsrc(base + j.pix_base + (unsigned long long)row0 * (uint32_t)j.w, (uint32_t)rows * (uint32_t)j.w * 4u);
 }
 
-__device__ __forceinline__ const EdtJob& job_of(const EdtArgs& a, uint32_t j) { return a.njobs == 1u ? a.job0 : a.jobs[j]; }
+struct WaveLds {
+  uint32_t F[RP * RP];
+};
 
-// Initial state and the first frontier: the contour features (features with a
-// non-feature neighbour, Algorithm 6 initialisation).  blockIdx.y = image.
-template <int CONN>
-__global__ __launch_bounds__(256) void k_init(EdtArgs a) {
-  __shared__ unsigned long long stage_mem[kWavesPerBlock][kStageCap];
-  const int w = threadIdx.x / kWave;
-  WaveStageT<unsigned long long> s = {stage_mem[w], (uint32_t)kStageCap, 0u};
-  const uint32_t j = blockIdx.y;
-  const EdtJob job = job_of(a, j);
-  const uint32_t npx = (uint32_t)job.h * (uint32_t)job.w;
-  unsigned long long* list1 = a.lists + a.npix;  // the first frontier is read by round 1: list parity 1, count slot 1
-  uint32_t contour = 0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < npx; base += stride) {
-    const uint32_t p = base + (uint32_t)lane();
-    const bool valid = p < npx;
-    bool c = false;
-    int y = 0, x = 0;
-    if (valid) {
-      y = (int)(p / (uint32_t)job.w);
-      x = (int)(p - (uint32_t)y * (uint32_t)job.w);
-      const bool feat = job.bin[p] == 0;
-      const unsigned long long k0 = feat ? (unsigned long long)pack_yx(y, x) : kNone;
-      a.key0[job.pix_base + p] = k0;
-      a.key1[job.pix_base + p] = k0;
-      a.stamp[job.pix_base + p] = 0u;
-      if (feat) {
+// Load the tile of `src` and its halo into LDS (kNone outside the image).
+__device__ void load_region(const uint32_t* src, const TileRef& tr, WaveLds& L) {
+  const EdtJob& j = tr.j;
+  const int y0 = tr.ty * TE, x0 = tr.tx * TE;
+  const int row0 = y0 > 0 ? y0 - 1 : 0;
+  const int row1 = y0 + TE + 1 < j.h ? y0 + TE + 1 : j.h;
+  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(src, j, row0, row1 - row0);
+  // 34 rows x 10 items: eight 16-byte chunks of the tile row, two halo words.
+  for (int idx = lane(); idx < RP * 10; idx += kWave) {
+    const int ry = idx / 10, item = idx - ry * 10;
+    const int y = y0 - 1 + ry;
+    const bool row_ok = y >= 0 && y < j.h;
+    const uint32_t rowoff = (uint32_t)(row_ok ? y - row0 : 0) * (uint32_t)j.w;
+    uint32_t* dst = &L.F[ry * RP];
+    if (item < 8) {
+      const int xs = x0 + item * 4;
+      v4u v = {kNone, kNone, kNone, kNone};
+      if (row_ok && xs < j.w) {
+        if (xs + 4 <= j.w) {
+          v = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, (rowoff + (uint32_t)xs) * 4u, 0, kSc1));
+        } else {
 #pragma unroll
-        for (int k = 0; k < CONN; ++k) {
-          int dy, dx;
-          nb_off<CONN>(k, dy, dx);
-          const int qy = y + dy, qx = x + dx;
-          if (qy >= 0 && qy < job.h && qx >= 0 && qx < job.w &&
-              job.bin[(uint32_t)qy * (uint32_t)job.w + (uint32_t)qx] != 0)
-            c = true;
+          for (int b = 0; b < 4; ++b)
+            if (xs + b < j.w) v[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, (rowoff + (uint32_t)(xs + b)) * 4u, 0, kSc1);
         }
       }
-      contour += c ? 1u : 0u;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) dst[1 + item * 4 + b] = v[b];
+    } else {
+      const int x = item == 8 ? x0 - 1 : x0 + TE;
+      uint32_t v = kNone;
+      if (row_ok && x >= 0 && x < j.w) v = __builtin_amdgcn_raw_buffer_load_b32(rs, (rowoff + (uint32_t)x) * 4u, 0, kSc1);
+      dst[item == 8 ? 0 : RP - 1] = v;
     }
-    stage_append(s, c, make_item(j, y, x), list1, a.counts + 64, a.npix, a.ovf);
   }
-  stage_flush(s, list1, a.counts + 64, a.npix, a.ovf);
+  wave_sync();
+}
+
+// One round of the operator on the tile in LDS.  Lane l handles column l & 31
+// of rows (l >> 5), (l >> 5) + 2, ...; the new values go to `dst` (the other
+// buffer), unconditionally.  Returns a bit mask of where something changed:
+// bit 0 anywhere, 1 row 0, 2 last row, 3 column 0, 4 last column, 5..8 the
+// corners (top-left, top-right, bottom-left, bottom-right); `changed` counts
+// the changed pixels.
+template <int CONN>
+__device__ uint32_t relax_tile(const WaveLds& L, uint32_t* dst, const TileRef& tr, uint32_t& changed) {
+  const EdtJob& j = tr.j;
+  const int y0 = tr.ty * TE, x0 = tr.tx * TE;
+  const int x = lane() & (TE - 1), yb = lane() >> 5;
+  const int qx = x0 + x;
+  const int row0 = y0 > 0 ? y0 - 1 : 0;
+  const int row1 = y0 + TE + 1 < j.h ? y0 + TE + 1 : j.h;
+  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(dst, j, row0, row1 - row0);
+  uint32_t any = 0, n = 0;
+#pragma unroll 4
+  for (int k = 0; k < TE / 2; ++k) {
+    const int y = yb + 2 * k;
+    const int qy = y0 + y;
+    const uint32_t old = L.F[(y + 1) * RP + x + 1];
+    uint32_t bd = 0xFFFFFFFFu, bf = kNone;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (CONN == 4 && dy != 0 && dx != 0) continue;
+        const uint32_t f = L.F[(y + 1 + dy) * RP + x + 1 + dx];
+        const int ey = qy - (int)(f >> 16), ex = qx - (int)(f & 0xffffu);
+        const uint32_t d = (uint32_t)(ey * ey + ex * ex);
+        const bool take = f != kNone && (d < bd || (d == bd && f < bf));
+        bd = take ? d : bd;
+        bf = take ? f : bf;
+      }
+    const bool inside = qy < j.h && qx < j.w;
+    if (inside)
+      __builtin_amdgcn_raw_buffer_store_b32(bf, rs, ((uint32_t)(qy - row0) * (uint32_t)j.w + (uint32_t)qx) * 4u, 0, kSc1);
+    if (inside && bf != old) {
+      n++;
+      any |= 1u;
+      if (y == 0) any |= 2u;
+      if (y == TE - 1) any |= 4u;
+      if (x == 0) any |= 8u;
+      if (x == TE - 1) any |= 16u;
+      if (y == 0 && x == 0) any |= 32u;
+      if (y == 0 && x == TE - 1) any |= 64u;
+      if (y == TE - 1 && x == 0) any |= 128u;
+      if (y == TE - 1 && x == TE - 1) any |= 256u;
+    }
+  }
+  changed += n;
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < 9; ++b)
+    if (ballot((any >> b) & 1u)) m |= 1u << b;
+  return m;
+}
+
+// Put tile t on the list of parity `par` (lanes with pred), once per round.
+__device__ __forceinline__ void mark_tiles(const EdtArgs& a, WaveStage& s, bool pred, uint32_t t, int par,
+                                           uint32_t* count) {
+  bool fresh = false;
+  if (pred) fresh = atomic_or(a.flags + (size_t)par * a.ntiles + t, 1u) == 0u;
+  stage_append(s, fresh, t, a.lists + (size_t)par * a.ntiles, count, a.ntiles, a.ovf);
+}
+
+// List the tiles that the changes of tile tr (mask m from relax_tile) reach:
+// itself and every neighbour whose halo holds a changed pixel.
+__device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const TileRef& tr, uint32_t m, int par,
+                                           uint32_t* count) {
+  const int l = lane();
+  int dy = 0, dx = 0;
+  bool want = false;
+  if (l == 0) {
+    want = (m & 1u) != 0u;
+  } else if (l < 9) {
+    // lanes 1..8: top, bottom, left, right, top-left, top-right, bottom-left, bottom-right
+    const int k = l - 1;
+    const uint32_t bit = k < 4 ? (2u << k) : (32u << (k - 4));
+    want = (m & bit) != 0u;
+    dy = k == 0 ? -1 : (k == 1 ? 1 : (k < 4 ? 0 : (k < 6 ? -1 : 1)));
+    dx = k < 2 ? 0 : (k == 2 ? -1 : (k == 3 ? 1 : ((k & 1) ? 1 : -1)));
+  }
+  const int ny = tr.ty + dy, nx = tr.tx + dx;
+  want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
+  mark_tiles(a, s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), par, count);
+}
+
+// Initial state (features carry themselves, everything else none) in both
+// buffers, the contour-feature count (Algorithm 6's initial queue), and the
+// first round's list: the tiles holding a non-feature pixel next to a feature,
+// which are exactly the pixels round 1 can change.  One wave per tile.
+template <int CONN>
+__global__ __launch_bounds__(256) void k_init(EdtArgs a) {
+  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  const int w = threadIdx.x / kWave;
+  const uint32_t t = blockIdx.x * kWavesPerBlock + w;
+  if (t >= a.ntiles) return;
+  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
+  const TileRef tr = tile_ref(a, t);
+  const EdtJob& j = tr.j;
+  const int x = lane() & (TE - 1), yb = lane() >> 5;
+  const int qx = tr.tx * TE + x;
+  uint32_t contour = 0;
+  bool reach = false;
+  if (lane() == 0) {
+    a.flags[t] = 0u;
+    a.flags[a.ntiles + t] = 0u;
+  }
+  for (int k = 0; k < TE / 2; ++k) {
+    const int qy = tr.ty * TE + yb + 2 * k;
+    if (qy >= j.h || qx >= j.w) continue;
+    const uint32_t p = (uint32_t)qy * (uint32_t)j.w + (uint32_t)qx;
+    const bool feat = j.bin[p] == 0;
+    bool nb_feat = false, nb_other = false;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if ((dy == 0 && dx == 0) || (CONN == 4 && dy != 0 && dx != 0)) continue;
+        const int ny = qy + dy, nx = qx + dx;
+        if (ny < 0 || ny >= j.h || nx < 0 || nx >= j.w) continue;
+        const bool f = j.bin[(uint32_t)ny * (uint32_t)j.w + (uint32_t)nx] == 0;
+        nb_feat |= f;
+        nb_other |= !f;
+      }
+    const uint32_t v = feat ? pack_yx(qy, qx) : kNone;
+    a.feat0[j.pix_base + p] = v;
+    a.feat1[j.pix_base + p] = v;
+    contour += (feat && nb_other) ? 1u : 0u;
+    reach |= !feat && nb_feat;
+  }
   uint32_t tot = contour;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-  if (lane() == 0) stat_add(a.stats, kStatSeeds, tot);
+  if (lane() == 0) {
+    stat_add(a.stats, kStatSeeds, tot);
+    stat_add(a.stats, kStatItems, tot);  // the first frontier
+  }
+  // round 1 reads list parity 1 with count slot 1 (the vote needs every lane)
+  const bool listed = ballot(reach) != 0;
+  mark_tiles(a, s, lane() == 0 && listed, t, 1, a.counts + 64);
+  stage_flush(s, a.lists + a.ntiles, a.counts + 64, a.ntiles, a.ovf);
 }
 
 template <int CONN>
 __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
-  __shared__ unsigned long long stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ WaveLds lds[kWavesPerBlock];
+  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
   __shared__ uint32_t nshared;
   const int w = threadIdx.x / kWave;
-  WaveStageT<unsigned long long> s = {stage_mem[w], (uint32_t)kStageCap, 0u};
+  WaveLds& L = lds[w];
+  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + w, nw = gridDim.x * kWavesPerBlock;
   uint32_t gen = 0;
-  unsigned long long items = 0, updates = 0;
+  unsigned long long changed = 0, visits = 0;
   uint32_t r = 1;
   for (;; ++r) {
     if (threadIdx.x == 0) nshared = cload(a.counts + (r % 3u) * 64u);
@@ -121,98 +268,64 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
     }
-    if (n > a.npix) n = a.npix;
-    items += n;
+    if (n > a.ntiles) n = a.ntiles;
     if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
-    const unsigned long long* rd = (r & 1u) ? a.key0 : a.key1;  // buffer (r-1)&1
-    unsigned long long* wr = (r & 1u) ? a.key1 : a.key0;        // buffer r&1
-    const unsigned long long* list = a.lists + (size_t)(r & 1u) * a.npix;
-    unsigned long long* nlist = a.lists + (size_t)((r + 1u) & 1u) * a.npix;
+    const uint32_t* rd = (r & 1u) ? a.feat0 : a.feat1;  // buffer (r-1)&1
+    uint32_t* wr = (r & 1u) ? a.feat1 : a.feat0;        // buffer r&1
+    const int par = (int)(r & 1u), npar = 1 - par;
+    const uint32_t* list = a.lists + (size_t)par * a.ntiles;
     uint32_t* ncount = a.counts + ((r + 1u) % 3u) * 64u;
-    for (uint32_t base = gw * kWave; base < n; base += nw * kWave) {
-      const uint32_t i = base + (uint32_t)lane();
-      const bool valid = i < n;
-      const unsigned long long it = valid ? cload(list + i) : 0ull;
-      const uint32_t j = (uint32_t)(it >> 32);
-      const int py = (int)((uint32_t)it >> 16), px = (int)((uint32_t)it & 0xffffu);
-      int h = 1, wd = 1;
-      uint32_t pb = 0;
-      if (valid) {
-        const EdtJob& job = job_of(a, j);
-        h = job.h;
-        wd = job.w;
-        pb = job.pix_base;
-      }
-      const uint32_t p = pb + (uint32_t)py * (uint32_t)wd + (uint32_t)px;
-      // Issue every independent access of the item together (one round trip
-      // each for: its own key and its neighbours' previous keys; the atomic
-      // mins; the stamps) instead of one chain per neighbour.
-      uint32_t q[CONN];
-      bool in[CONN];
-      unsigned long long prev[CONN];
-#pragma unroll
-      for (int k = 0; k < CONN; ++k) {
-        int dy, dx;
-        nb_off<CONN>(k, dy, dx);
-        const int qy = py + dy, qx = px + dx;
-        in[k] = valid && qy >= 0 && qy < h && qx >= 0 && qx < wd;
-        q[k] = in[k] ? pb + (uint32_t)qy * (uint32_t)wd + (uint32_t)qx : 0u;
-      }
-      const unsigned long long sk = valid ? cload(rd + p) : kNone;
-#pragma unroll
-      for (int k = 0; k < CONN; ++k) prev[k] = in[k] ? cload(rd + q[k]) : 0ull;
-      if (valid && r > 1u) atomic_min(wr + p, sk);  // catch up: this pixel changed in round r-1
-      const uint32_t f = (uint32_t)sk;
-      const int fy = (int)(f >> 16), fx = (int)(f & 0xffffu);
-      unsigned long long cand[CONN], old[CONN];
-#pragma unroll
-      for (int k = 0; k < CONN; ++k) {
-        int dy, dx;
-        nb_off<CONN>(k, dy, dx);
-        const int ey = py + dy - fy, ex = px + dx - fx;
-        cand[k] = ((unsigned long long)(uint32_t)(ey * ey + ex * ex) << 32) | f;
-        old[k] = (in[k] && cand[k] < prev[k]) ? atomic_min(wr + q[k], cand[k]) : 0ull;
-      }
-      bool fresh[CONN];
-#pragma unroll
-      for (int k = 0; k < CONN; ++k) {
-        const bool improved = in[k] && cand[k] < prev[k] && cand[k] < old[k];
-        fresh[k] = improved ? atomic_max(a.stamp + q[k], r) < r : false;
-        updates += fresh[k] ? 1u : 0u;
-      }
-#pragma unroll
-      for (int k = 0; k < CONN; ++k) {
-        int dy, dx;
-        nb_off<CONN>(k, dy, dx);
-        stage_append(s, fresh[k], make_item(j, py + dy, px + dx), nlist, ncount, a.npix, a.ovf);
-      }
+    for (uint32_t i = gw; i < n; i += nw) {
+      const uint32_t t = cload(list + i);
+      if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
+      const TileRef tr = tile_ref(a, t);
+      load_region(rd, tr, L);
+      uint32_t c = 0;
+      const uint32_t m = relax_tile<CONN>(L, wr, tr, c);
+      changed += c;
+      visits++;
+      mark_reach(a, s, tr, m, npar, ncount);
     }
-    stage_flush(s, nlist, ncount, a.npix, a.ovf);
+    stage_flush(s, a.lists + (size_t)npar * a.ntiles, ncount, a.ntiles, a.ovf);
     if (!grid_barrier(a.bar, gen, a.stats)) return;
   }
-  // Finalize: buffer (r-1)&1 holds the state after the last round.
-  const unsigned long long* fin = (r & 1u) ? a.key0 : a.key1;
+  // Both buffers now agree everywhere; write the outputs.
+  const uint32_t* fin = a.feat0;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t j = 0; j < a.njobs; ++j) {
-    const EdtJob& job = job_of(a, j);
-    const uint32_t npx = (uint32_t)job.h * (uint32_t)job.w;
+  for (uint32_t jj = 0; jj < a.njobs; ++jj) {
+    const EdtJob& j = a.njobs == 1u ? a.job0 : a.jobs[jj];
+    const uint32_t npx = (uint32_t)j.h * (uint32_t)j.w;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
-      const unsigned long long k = cload(fin + job.pix_base + p);
-      if (k == kNone) {
-        job.sqdist[p] = -1;
-        job.nearest[p] = -1;
+      const uint32_t f = cload(fin + j.pix_base + p);
+      if (f == kNone) {
+        j.sqdist[p] = -1;
+        j.nearest[p] = -1;
       } else {
-        const uint32_t f = (uint32_t)k;
-        job.sqdist[p] = (int32_t)(k >> 32);
-        job.nearest[p] = (int32_t)((f >> 16) * (uint32_t)job.w + (f & 0xffffu));
+        const int y = (int)(p / (uint32_t)j.w), x = (int)(p - (uint32_t)y * (uint32_t)j.w);
+        const int ey = y - (int)(f >> 16), ex = x - (int)(f & 0xffffu);
+        j.sqdist[p] = ey * ey + ex * ex;
+        j.nearest[p] = (int32_t)((f >> 16) * (uint32_t)j.w + (f & 0xffffu));
       }
     }
   }
-  for (int o = 32; o > 0; o >>= 1) updates += __shfl_xor(updates, o);
-  if (lane() == 0) stat_add(a.stats, kStatUpdates, updates);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    stat_add(a.stats, kStatItems, items);
-    stat_add(a.stats, kStatRounds, r >= 2u ? r - 2u : 0u);
+  for (int o = 32; o > 0; o >>= 1) changed += __shfl_xor(changed, o);
+  if (lane() == 0) {
+    stat_add(a.stats, kStatItems, changed);  // pixels changed in a round join the next frontier
+    stat_add(a.stats, kStatUpdates, changed);
+    stat_add(a.stats, kStatSweeps, visits);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatRounds, r >= 2u ? r - 2u : 0u);
+}
+
+// Image of every global tile, by binary search over the images' first tiles.
+__global__ void k_tile_job(const EdtJob* jobs, uint32_t njobs, uint32_t* tile_job, uint32_t ntiles) {
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1u) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].tile_base <= t) lo = mid; else hi = mid;
+    }
+    tile_job[t] = lo;
   }
 }
 
@@ -220,16 +333,20 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
 
 int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err) {
   using namespace edt;
-  // blocks per image: enough to fill the device when spread over the images
-  uint32_t per_job = (2048u + a.njobs - 1u) / a.njobs;
-  const uint32_t avg = (a.npix / a.njobs + 255u) / 256u;
-  if (per_job > avg) per_job = avg;
-  if (per_job < 1u) per_job = 1u;
+  if (a.njobs > 1u) {
+    const uint32_t b = (a.ntiles + 255u) / 256u;
+    hipLaunchKernelGGL(k_tile_job, dim3(b < 1024u ? b : 1024u), dim3(256), 0, stream, a.jobs, a.njobs, a.tile_job, a.ntiles);
+    if (hipGetLastError() != hipSuccess) {
+      *err = "tile map launch failed";
+      return -1;
+    }
+  }
+  const uint32_t init_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   rec->begin(4, stream);
   if (conn == 8)
-    hipLaunchKernelGGL(k_init<8>, dim3(per_job, a.njobs), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_init<8>, dim3(init_blocks), dim3(256), 0, stream, a);
   else
-    hipLaunchKernelGGL(k_init<4>, dim3(per_job, a.njobs), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL(k_init<4>, dim3(init_blocks), dim3(256), 0, stream, a);
   rec->end(stream);
   if (hipGetLastError() != hipSuccess) {
     *err = "EDT init launch failed";
@@ -247,7 +364,7 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
   EdtArgs args = a;
   void* kargs[] = {&args};
   rec->begin(5, stream);
-  const hipError_t le = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), kargs, 0, stream);
+  const hipError_t le = launch_persistent(fn, blocks, kargs, stream);
   rec->end(stream);
   if (le != hipSuccess) {
     *err = "EDT rounds launch failed";
@@ -265,6 +382,13 @@ uint32_t persistent_grid(const void* fn, int per_cu, int cus) {
   }
   if (lim < 1) lim = 1;
   return (uint32_t)lim * (uint32_t)cus;
+}
+
+hipError_t launch_persistent(const void* fn, uint32_t blocks, void** args, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
+    return hipLaunchKernel(fn, dim3(blocks), dim3(256), args, 0, s);
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, s);
 }
 
 // Zero a range of 32-bit words with a kernel (no memset node, so the sequence

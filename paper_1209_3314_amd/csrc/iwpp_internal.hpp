@@ -44,22 +44,27 @@ struct EdtJob {
   int32_t* sqdist;
   int32_t* nearest;
   int32_t h, w;
-  uint32_t pix_base;  // first global pixel id of this image
+  int32_t tiles_y, tiles_x;  // 32x32 tiles
+  uint32_t tile_base;        // first global tile id of this image
   uint32_t pad;
+  unsigned long long pix_base;  // first global pixel id of this image
 };
 
-// Distance-transform launch arguments.  Global pixel id = pix_base + y*w + x.
+// Distance-transform launch arguments.  Global pixel id = pix_base + y*w + x;
+// global tile ids run over all images.
 struct EdtArgs {
   EdtJob job0;                // the image when njobs == 1
   const EdtJob* jobs;         // [njobs] device table when njobs > 1
+  uint32_t* tile_job;         // [ntiles] image of each global tile when njobs > 1
   uint32_t njobs;
-  uint32_t npix;              // total pixels over all images
-  unsigned long long* key0;   // [npix] packed (d2 << 32 | y << 16 | x), ~0 = none
-  unsigned long long* key1;   // [npix]
-  uint32_t* stamp;            // [npix] last round that listed the pixel
-  unsigned long long* lists;  // [2][npix] frontier items (job << 32 | y << 16 | x)
+  uint32_t ntiles;
+  unsigned long long npix;    // total pixels over all images
+  uint32_t* feat0;            // [npix] nearest feature (y << 16 | x), ~0 = none; round parity 0
+  uint32_t* feat1;            // [npix] round parity 1
+  uint32_t* flags;            // [2][ntiles] "already listed" per round parity
+  uint32_t* lists;            // [2][ntiles] active tiles per round parity
   uint32_t* counts;           // [3][64]
-  uint32_t* ovf;              // [64] never set: a frontier holds each pixel once
+  uint32_t* ovf;              // [64] never set: a list holds each tile once
   GridBarrier* bar;
   unsigned long long* stats;
 };
@@ -101,5 +106,12 @@ int zero_words(uint32_t* p, size_t nwords, hipStream_t stream);
 // grids sized from the raw figure (8 per CU for a 16 KiB kernel) were measured
 // not to be co-resident on MI355X, while these caps are.
 uint32_t persistent_grid(const void* fn, int per_cu, int cus);
+
+// Launch a persistent kernel: a cooperative launch (the runtime checks that the
+// whole grid is resident), or a plain launch of the same grid while `s` is being
+// captured into a graph.  Inside a graph, residency then rests on the grid
+// fitting the device when the graph runs alone; a grid that does not fit makes
+// the grid barrier time out and report an error instead of waiting forever.
+hipError_t launch_persistent(const void* fn, uint32_t blocks, void** args, hipStream_t s);
 
 }  // namespace iwpp

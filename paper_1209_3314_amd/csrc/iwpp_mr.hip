@@ -617,7 +617,7 @@ int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stre
   MrArgs args = a;
   void* kargs[] = {&args};
   rec->begin(3, stream);
-  const hipError_t le = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), kargs, 0, stream);
+  const hipError_t le = launch_persistent(fn, blocks, kargs, stream);
   rec->end(stream);
   if (le != hipSuccess) {
     *err = "propagation launch failed";

@@ -1,0 +1,601 @@
+// Serving loop: jobs arrive one by one from the host, are admitted against a
+// device-memory budget and a slot limit, uploaded on a copy stream, run in
+// batches on a compute stream (all admitted jobs that are not yet running
+// form the next batch: continuous batching) and downloaded on a second copy
+// stream.  The paper's runtime hands independent tiles to whichever device
+// is free, first come first served (Sec. 4); here one device takes them in
+// batches, which fills it with many small tiles at once.
+//
+// Concurrency: one worker thread owns the device side (streams, arena,
+// batches); submit/poll/drain/stats take a mutex shared with it.  At most two
+// batches are queued on the compute stream, so the device goes from one batch
+// to the next without a host round trip while later arrivals still join the
+// batch after.  Batches share the context's fixed area and one scratch buffer:
+// they run one after another in stream order.
+#include <hip/hip_runtime.h>
+#include <time.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/iwpp.h"
+#include "iwpp_device.hpp"
+#include "iwpp_internal.hpp"
+#include "iwpp_runtime.hpp"
+
+namespace {
+
+using iwpp::rt::align256;
+
+int64_t mono_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (int64_t)ts.tv_sec * 1000000000ll + ts.tv_nsec;
+}
+
+// First-fit allocator over one device range, 256-byte granules, coalescing frees.
+class Arena {
+ public:
+  void init(size_t bytes) {
+    free_.clear();
+    size_ = bytes & ~size_t(255);
+    if (size_) free_[0] = size_;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align256(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used_ += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align256(bytes ? bytes : 1);
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;  // offset -> length
+  size_t size_ = 0;
+  size_t used_ = 0;
+};
+
+size_t job_buffer_bytes(const iwpp_job& j) {
+  const size_t np = (size_t)j.height * (size_t)j.width;
+  // recon: mask | marker (the output is written in place over the marker copy)
+  // EDT: binary | sqdist | nearest
+  return j.op == IWPP_OP_RECON ? 2 * align256(np) : align256(np) + 2 * align256(4 * np);
+}
+
+struct SJob {
+  iwpp_job host{};  // caller's host buffers
+  int64_t arrival_ns = 0;
+  int64_t done_ns = 0;
+  int32_t state = IWPP_JOB_QUEUED;
+  size_t off = 0, bytes = 0;
+  iwpp_job dev{};  // the same job on device buffers
+};
+
+struct Batch {
+  std::vector<uint64_t> tickets;
+  hipEvent_t up = nullptr, done = nullptr, down = nullptr;
+  int slot = -1;
+  size_t scratch = 0;
+};
+
+constexpr int kSlots = 3;           // pinned table/statistics slots (≤ 2 batches in flight + 1)
+constexpr int kMaxQueuedBatches = 2;
+constexpr size_t kStatWords = iwpp::kStatShards * iwpp::kStatFields;
+
+}  // namespace
+
+struct iwpp_server {
+  iwpp_ctx* ctx = nullptr;
+  iwpp_server_options opt{};
+  size_t budget = 0, scratch_cap = 0;
+  uint8_t* arena_base = nullptr;
+  uint8_t* scratch = nullptr;
+  hipStream_t h2d = nullptr, comp = nullptr, d2h = nullptr;
+  uint8_t* pinned = nullptr;  // kSlots x (tables | stats)
+  size_t slot_bytes = 0, table_cap = 0;
+  bool slot_busy[kSlots] = {};
+  std::vector<hipEvent_t> event_pool;
+
+  // worker-only state
+  iwpp_ctx wctx;  // the worker's view of the context (own error string)
+  Arena arena;
+  std::deque<uint64_t> admitted;
+  std::deque<Batch> inflight;
+  bool broken = false;
+
+  // shared state
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<SJob> jobs;  // index = ticket
+  std::deque<uint64_t> pending;
+  bool stop = false;
+  std::string error;
+  iwpp_server_stats st{};
+  std::thread worker;
+
+  hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  void put_event(hipEvent_t e) {
+    if (e) event_pool.push_back(e);
+  }
+  uint8_t* slot_tables(int s) { return pinned + (size_t)s * slot_bytes; }
+  unsigned long long* slot_stats(int s) {
+    return reinterpret_cast<unsigned long long*>(pinned + (size_t)s * slot_bytes + table_cap);
+  }
+
+  void set_error(const std::string& m) {
+    std::lock_guard<std::mutex> g(mu);
+    if (error.empty()) error = m;
+  }
+
+  // Finish the oldest batches whose downloads are complete.
+  bool complete() {
+    bool progress = false;
+    while (!inflight.empty()) {
+      Batch& b = inflight.front();
+      const hipError_t q = hipEventQuery(b.down);
+      if (q == hipErrorNotReady) break;
+      const int64_t now = mono_ns();
+      bool ok = q == hipSuccess;
+      if (!ok) {
+        (void)hipGetLastError();
+        broken = true;
+        set_error("serving: device error in a batch");
+      } else {
+        iwpp_stats s;
+        iwpp::rt::fold_stats(slot_stats(b.slot), 3, &s);
+        if (s.status != IWPP_OK) {
+          ok = false;
+          set_error("serving: a batch hit a kernel safety limit");
+        }
+      }
+      {
+        std::lock_guard<std::mutex> g(mu);
+        for (uint64_t t : b.tickets) {
+          SJob& j = jobs[t];
+          j.state = ok ? IWPP_JOB_DONE : IWPP_JOB_FAILED;
+          j.done_ns = now;
+          arena.release(j.off, j.bytes);
+          if (ok)
+            st.completed++;
+          else
+            st.failed++;
+          st.admitted_now--;
+        }
+      }
+      slot_busy[b.slot] = false;
+      put_event(b.up);
+      put_event(b.done);
+      put_event(b.down);
+      inflight.pop_front();
+      progress = true;
+      cv.notify_all();
+    }
+    return progress;
+  }
+
+  // Admit queued jobs in arrival order while memory and slots allow.
+  bool admit() {
+    bool progress = false;
+    for (;;) {
+      uint64_t t;
+      SJob* j;
+      {
+        std::lock_guard<std::mutex> g(mu);
+        if (pending.empty()) break;
+        t = pending.front();
+        j = &jobs[t];
+        if (broken) {
+          pending.pop_front();
+          j->state = IWPP_JOB_FAILED;
+          j->done_ns = mono_ns();
+          st.failed++;
+          st.queued_now--;
+          cv.notify_all();
+          progress = true;
+          continue;
+        }
+        if (st.admitted_now >= opt.max_inflight) break;
+      }
+      const size_t bytes = job_buffer_bytes(j->host);
+      size_t off = 0;
+      if (!arena.alloc(bytes, &off)) break;
+      const size_t np = (size_t)j->host.height * (size_t)j->host.width;
+      uint8_t* base = arena_base + off;
+      iwpp_job d = j->host;
+      bool ok = true;
+      if (d.op == IWPP_OP_RECON) {
+        uint8_t* mask = base;
+        uint8_t* marker = base + align256(np);  // overwritten by the result
+        d.in1 = mask;
+        d.in0 = marker;
+        d.out0 = marker;
+        ok = hipMemcpyAsync(mask, j->host.in1, np, hipMemcpyHostToDevice, h2d) == hipSuccess &&
+             hipMemcpyAsync(marker, j->host.in0, np, hipMemcpyHostToDevice, h2d) == hipSuccess;
+      } else {
+        d.in0 = base;
+        d.out0 = base + align256(np);
+        d.out1 = base + align256(np) + align256(4 * np);
+        ok = hipMemcpyAsync(base, j->host.in0, np, hipMemcpyHostToDevice, h2d) == hipSuccess;
+      }
+      if (!ok) {
+        (void)hipGetLastError();
+        arena.release(off, bytes);
+        broken = true;
+        set_error("serving: upload failed");
+        continue;  // the job fails on the next pass through `broken`
+      }
+      {
+        std::lock_guard<std::mutex> g(mu);
+        pending.pop_front();
+        j->off = off;
+        j->bytes = bytes;
+        j->dev = d;
+        j->state = IWPP_JOB_ADMITTED;
+        st.queued_now--;
+        st.admitted_now++;
+        const int64_t used = (int64_t)(arena.used() + scratch_cap);
+        if (used > st.peak_bytes) st.peak_bytes = used;
+      }
+      admitted.push_back(t);
+      progress = true;
+    }
+    return progress;
+  }
+
+  // Launch the admitted jobs as one batch when the compute stream has room.
+  bool launch() {
+    if (admitted.empty() || (int)inflight.size() >= kMaxQueuedBatches || broken) return false;
+    int slot = -1;
+    for (int s = 0; s < kSlots; ++s)
+      if (!slot_busy[s]) {
+        slot = s;
+        break;
+      }
+    if (slot < 0) return false;
+    std::vector<iwpp_job> dj;
+    std::vector<uint64_t> tk;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      for (uint64_t t : admitted) {
+        if ((int)dj.size() >= opt.max_batch) break;
+        dj.push_back(jobs[t].dev);
+        tk.push_back(t);
+      }
+    }
+    iwpp::rt::Plan plan;
+    size_t n = dj.size();
+    for (;;) {  // shrink the batch until its scratch and tables fit
+      plan = iwpp::rt::Plan();
+      if (iwpp::rt::build_plan(&wctx, dj.data(), (int32_t)n, "serve", plan) != IWPP_OK) {
+        broken = true;
+        set_error(wctx.err);
+        return false;
+      }
+      if (align256(plan.scratch_bytes) + plan.table_bytes <= scratch_cap && plan.table_bytes <= table_cap) break;
+      if (n == 1) {
+        broken = true;
+        set_error("serving: a job does not fit the scratch area");
+        return false;
+      }
+      n = n / 2;
+    }
+    tk.resize(n);
+    Batch b;
+    b.tickets = tk;
+    b.slot = slot;
+    b.up = get_event();
+    b.done = get_event();
+    b.down = get_event();
+    const size_t sb = align256(plan.scratch_bytes);
+    uint8_t* tables = scratch + sb;
+    iwpp::rt::pack_tables(plan, slot_tables(slot));
+    iwpp::Recorder off;
+    bool ok = b.up && b.done && b.down && hipEventRecord(b.up, h2d) == hipSuccess &&
+              hipStreamWaitEvent(comp, b.up, 0) == hipSuccess;
+    if (ok && plan.table_bytes)
+      ok = hipMemcpyAsync(tables, slot_tables(slot), plan.table_bytes, hipMemcpyHostToDevice, comp) == hipSuccess;
+    bool first = true;
+    for (const iwpp::rt::Group& g : plan.groups) {
+      if (!ok) break;
+      ok = iwpp::rt::launch_group(&wctx, g, scratch, wctx.fixed, tables, comp, first, &off) == IWPP_OK;
+      first = false;
+    }
+    ok = ok &&
+         hipMemcpyAsync(slot_stats(slot), wctx.fixed + iwpp::rt::kOffStats, kStatWords * 8, hipMemcpyDeviceToHost,
+                        comp) == hipSuccess &&
+         hipEventRecord(b.done, comp) == hipSuccess && hipStreamWaitEvent(d2h, b.done, 0) == hipSuccess;
+    if (ok) {
+      std::lock_guard<std::mutex> g(mu);
+      for (uint64_t t : tk) {
+        SJob& j = jobs[t];
+        const size_t np = (size_t)j.host.height * (size_t)j.host.width;
+        if (j.host.op == IWPP_OP_RECON) {
+          ok = ok && hipMemcpyAsync(j.host.out0, j.dev.out0, np, hipMemcpyDeviceToHost, d2h) == hipSuccess;
+        } else {
+          ok = ok && hipMemcpyAsync(j.host.out0, j.dev.out0, 4 * np, hipMemcpyDeviceToHost, d2h) == hipSuccess &&
+               hipMemcpyAsync(j.host.out1, j.dev.out1, 4 * np, hipMemcpyDeviceToHost, d2h) == hipSuccess;
+        }
+        j.state = IWPP_JOB_RUNNING;
+      }
+      st.batches++;
+      if ((int64_t)n > st.max_batch_jobs) st.max_batch_jobs = (int64_t)n;
+    }
+    ok = ok && hipEventRecord(b.down, d2h) == hipSuccess;
+    for (size_t i = 0; i < n; ++i) admitted.pop_front();
+    slot_busy[slot] = true;
+    if (!ok) {
+      (void)hipGetLastError();
+      broken = true;
+      set_error(std::string("serving: batch launch failed: ") + wctx.err);
+      // Wait for what was enqueued, then let complete() fail the batch.
+      (void)hipStreamSynchronize(comp);
+      (void)hipStreamSynchronize(d2h);
+      (void)hipGetLastError();
+    }
+    inflight.push_back(b);
+    return true;
+  }
+
+  void run() {
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+      bool progress = complete();
+      progress |= admit();
+      progress |= launch();
+      if (broken) {
+        // Fail everything admitted but not launched.
+        std::lock_guard<std::mutex> g(mu);
+        while (!admitted.empty()) {
+          SJob& j = jobs[admitted.front()];
+          admitted.pop_front();
+          j.state = IWPP_JOB_FAILED;
+          j.done_ns = mono_ns();
+          arena.release(j.off, j.bytes);
+          st.failed++;
+          st.admitted_now--;
+          progress = true;
+        }
+        cv.notify_all();
+      }
+      if (!progress) {
+        std::unique_lock<std::mutex> g(mu);
+        if (stop && pending.empty() && admitted.empty() && inflight.empty()) break;
+        // Sleep briefly; a submit wakes the loop at once.
+        cv.wait_for(g, std::chrono::microseconds(inflight.empty() ? 500 : 20));
+      }
+    }
+  }
+};
+
+namespace {
+
+void free_server(iwpp_server* s) {
+  for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  if (s->pinned) (void)hipHostFree(s->pinned);
+  if (s->h2d) (void)hipStreamDestroy(s->h2d);
+  if (s->comp) (void)hipStreamDestroy(s->comp);
+  if (s->d2h) (void)hipStreamDestroy(s->d2h);
+  if (s->arena_base) (void)hipFree(s->arena_base);
+  if (s->scratch) (void)hipFree(s->scratch);
+  (void)hipGetLastError();
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_server** out) {
+  using iwpp::rt::fail;
+  if (!ctx) return IWPP_EINVAL;
+  if (!out) return fail(ctx, IWPP_EINVAL, "server_start: out is NULL");
+  *out = nullptr;
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "server_start: the context already runs a server");
+  iwpp_server_options o{};
+  if (opt) o = *opt;
+  if (o.hbm_budget_bytes < 0 || o.scratch_bytes < 0 || o.max_inflight < 0 || o.max_batch < 0)
+    return fail(ctx, IWPP_EINVAL, "server_start: negative option");
+  if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = 64ll << 30;
+  if (o.max_inflight == 0) o.max_inflight = 4096;
+  if (o.max_batch == 0) o.max_batch = 512;
+  if (o.scratch_bytes == 0) o.scratch_bytes = o.hbm_budget_bytes / 4;
+  if (o.scratch_bytes >= o.hbm_budget_bytes || o.hbm_budget_bytes < (8ll << 20))
+    return fail(ctx, IWPP_EINVAL, "server_start: budget below 8 MiB or scratch not below the budget");
+  iwpp::rt::DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, IWPP_EDEVICE, "server_start: cannot select the context's device");
+  iwpp_server* s = new (std::nothrow) iwpp_server();
+  if (!s) return fail(ctx, IWPP_ENOMEM, "server_start: out of host memory");
+  s->ctx = ctx;
+  s->opt = o;
+  s->wctx.device = ctx->device;
+  s->wctx.opt = ctx->opt;
+  s->wctx.opt.profile = 0;
+  s->wctx.fixed = ctx->fixed;
+  s->budget = (size_t)o.hbm_budget_bytes;
+  s->scratch_cap = (size_t)o.scratch_bytes & ~size_t(255);
+  s->table_cap = align256((size_t)o.max_batch * (sizeof(iwpp::EdtJob) > sizeof(iwpp::MrJob) ? sizeof(iwpp::EdtJob)
+                                                                                                 : sizeof(iwpp::MrJob)) +
+                          4 * 256);
+  s->slot_bytes = s->table_cap + align256(kStatWords * 8);
+  void* a = nullptr;
+  void* sc = nullptr;
+  void* pin = nullptr;
+  const size_t arena_bytes = s->budget - s->scratch_cap;
+  bool ok = hipMalloc(&a, arena_bytes) == hipSuccess;
+  if (ok) s->arena_base = static_cast<uint8_t*>(a);
+  ok = ok && hipMalloc(&sc, s->scratch_cap) == hipSuccess;
+  if (ok) s->scratch = static_cast<uint8_t*>(sc);
+  ok = ok && hipHostMalloc(&pin, s->slot_bytes * kSlots, hipHostMallocDefault) == hipSuccess;
+  if (ok) s->pinned = static_cast<uint8_t*>(pin);
+  if (!ok) {
+    free_server(s);
+    return fail(ctx, IWPP_ENOMEM, "server_start: cannot allocate the budget on the device");
+  }
+  ok = hipStreamCreateWithFlags(&s->h2d, hipStreamNonBlocking) == hipSuccess &&
+       hipStreamCreateWithFlags(&s->comp, hipStreamNonBlocking) == hipSuccess &&
+       hipStreamCreateWithFlags(&s->d2h, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    free_server(s);
+    return fail(ctx, IWPP_EDEVICE, "server_start: stream creation failed");
+  }
+  s->arena.init(arena_bytes);
+  try {
+    s->worker = std::thread([s] { s->run(); });
+  } catch (...) {
+    free_server(s);
+    return fail(ctx, IWPP_ENOMEM, "server_start: cannot start the worker thread");
+  }
+  ctx->server = s;
+  *out = s;
+  return IWPP_OK;
+}
+
+int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_ns, uint64_t* ticket) {
+  using iwpp::rt::fail;
+  if (!s) return IWPP_EINVAL;
+  iwpp_ctx* ctx = s->ctx;
+  if (!job || !ticket) return fail(ctx, IWPP_EINVAL, "server_submit: NULL argument");
+  const iwpp_job& j = *job;
+  if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_EDT) return fail(ctx, IWPP_EINVAL, "server_submit: op must be RECON or EDT");
+  if (j.conn != 4 && j.conn != 8) return fail(ctx, IWPP_EINVAL, "server_submit: conn must be 4 or 8");
+  if (j.height < 1 || j.width < 1) return fail(ctx, IWPP_EINVAL, "server_submit: height and width must be >= 1");
+  if (j.op == IWPP_OP_RECON && (!j.in0 || !j.in1 || !j.out0 || j.out1))
+    return fail(ctx, IWPP_EINVAL, "server_submit: reconstruction needs in0, in1, out0 and no out1");
+  if (j.op == IWPP_OP_EDT && (!j.in0 || j.in1 || !j.out0 || !j.out1))
+    return fail(ctx, IWPP_EINVAL, "server_submit: EDT needs in0, out0, out1 and no in1");
+  if (j.op == IWPP_OP_EDT && (j.height > 32767 || j.width > 32767))
+    return fail(ctx, IWPP_EINVAL, "server_submit: EDT height and width must be <= 32767");
+  if ((uint64_t)j.height * (uint64_t)j.width > 0xFFFFFFFFull)
+    return fail(ctx, IWPP_EINVAL, "server_submit: image larger than 2^32 - 1 pixels");
+  const size_t need = job_buffer_bytes(j);
+  const size_t sc = iwpp::rt::job_scratch_bytes(j.op, j.height, j.width) + 64 * 256;
+  if (need > s->arena.size() || sc > s->scratch_cap)
+    return fail(ctx, IWPP_EINVAL, "server_submit: the job can never fit the server's memory budget");
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) return fail(ctx, IWPP_EBUSY, "server_submit: the server is stopping");
+    SJob sj;
+    sj.host = j;
+    sj.arrival_ns = arrival_ns > 0 ? arrival_ns : mono_ns();
+    *ticket = (uint64_t)s->jobs.size();
+    s->jobs.push_back(sj);
+    s->pending.push_back(*ticket);
+    s->st.submitted++;
+    s->st.queued_now++;
+  }
+  s->cv.notify_all();
+  return IWPP_OK;
+}
+
+int32_t iwpp_server_poll(iwpp_server* s, uint64_t ticket, int32_t* state, double* latency_ms) {
+  using iwpp::rt::fail;
+  if (!s) return IWPP_EINVAL;
+  if (!state) return fail(s->ctx, IWPP_EINVAL, "server_poll: state is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  if (ticket >= s->jobs.size()) return fail(s->ctx, IWPP_EINVAL, "server_poll: unknown ticket");
+  const SJob& j = s->jobs[ticket];
+  *state = j.state;
+  if (latency_ms)
+    *latency_ms = (j.state == IWPP_JOB_DONE || j.state == IWPP_JOB_FAILED) ? (j.done_ns - j.arrival_ns) * 1e-6 : -1.0;
+  if (j.state == IWPP_JOB_FAILED) s->ctx->err = s->error;
+  return IWPP_OK;
+}
+
+int32_t iwpp_server_drain(iwpp_server* s, int64_t timeout_ms) {
+  using iwpp::rt::fail;
+  if (!s) return IWPP_EINVAL;
+  std::unique_lock<std::mutex> g(s->mu);
+  auto done = [s] { return s->st.completed + s->st.failed == s->st.submitted; };
+  if (timeout_ms < 0) {
+    s->cv.wait(g, done);
+  } else if (!s->cv.wait_for(g, std::chrono::milliseconds(timeout_ms), done)) {
+    s->ctx->err = "server_drain: timed out";
+    return IWPP_EBUSY;
+  }
+  if (s->st.failed) {
+    s->ctx->err = s->error;
+    return IWPP_EDEVICE;
+  }
+  return IWPP_OK;
+}
+
+int32_t iwpp_server_get_stats(iwpp_server* s, iwpp_server_stats* out) {
+  if (!s) return IWPP_EINVAL;
+  if (!out) return iwpp::rt::fail(s->ctx, IWPP_EINVAL, "server_get_stats: out is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  *out = s->st;
+  return IWPP_OK;
+}
+
+int32_t iwpp_server_stop(iwpp_server* s) {
+  if (!s) return IWPP_EINVAL;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  iwpp_ctx* ctx = s->ctx;
+  const bool failed = s->st.failed != 0;
+  std::string err = s->error;
+  {
+    iwpp::rt::DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(s->comp);
+    (void)hipStreamSynchronize(s->d2h);
+    free_server(s);
+  }
+  ctx->server = nullptr;
+  if (failed) {
+    ctx->err = err;
+    return IWPP_EDEVICE;
+  }
+  return IWPP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+"""Autotuner for the library's launch options.
+
+The options of ``iwpp_options`` change only speed, never results: the
+persistent grid size (workgroups of the propagation kernels, the paper's
+blocks-per-multiprocessor knob of Sec. 5.2), the sweep caps per tile visit and
+per seed-pass tile (the number of initial raster scans that Table 1 varies) and
+the work-list capacity (the global queue size of Sec. 3.2).  The tuner times a
+small grid of candidates per (operation, connectivity, size bucket) on
+synthetic inputs of that bucket, checks that every candidate's output equals
+the default options' output byte for byte, keeps the fastest, and caches the
+choice as JSON keyed by device and library version.  ``TunedContext`` applies
+the cached choice before each call.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import Context, _lib
+
+DEFAULTS = {"persistent_blocks": 0, "mr_max_sweeps": 0, "mr_seed_sweeps": 0, "mr_list_capacity": 0}
+
+# Candidate grids.  0 means the library default (device-filling grid, 64 sweeps).
+GRID = {
+    "recon": [{"persistent_blocks": pb, "mr_max_sweeps": ms, "mr_seed_sweeps": ss}
+              for pb in (0, 256, 512) for ms in (2, 8, 0) for ss in (2, 8, 0)],
+    "edt": [{"persistent_blocks": pb} for pb in (0, 128, 256, 512)],
+}
+
+
+def bucket(op: str, conn: int, pixels: int) -> str:
+    """Size bucket of a call: operation, connectivity and the next power of
+    two of the pixel count (at least 2^12)."""
+    if op not in ("recon", "edt", "batch"):
+        raise ValueError(f"unknown op {op!r}")
+    k = max(12, math.ceil(math.log2(max(1, pixels))))
+    return f"{op}/{conn}/2^{k}"
+
+
+def bucket_side(key: str) -> tuple:
+    """A near-square (h, w) whose pixel count fills the bucket `key`."""
+    k = int(key.rsplit("2^", 1)[1])
+    h = 1 << (k // 2)
+    return h, (1 << k) // h
+
+
+def default_cache_path(device_name: str) -> str:
+    base = os.environ.get("IWPP_TUNE_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "iwpp")
+    safe = "".join(c if c.isalnum() or c in "-_." else "_" for c in device_name)
+    return os.path.join(base, f"tune_{safe}.json")
+
+
+class TuneCache:
+    """JSON cache {"version": v, "device": name, "entries": {bucket: {options, ms, default_ms}}}."""
+
+    def __init__(self, path: str, device_name: str, version: int):
+        self.path = path
+        self.device = device_name
+        self.version = version
+        self.entries: dict = {}
+        if os.path.exists(path):
+            try:
+                with open(path) as f:
+                    d = json.load(f)
+                if d.get("version") == version and d.get("device") == device_name:
+                    self.entries = dict(d.get("entries", {}))
+            except (OSError, ValueError):
+                self.entries = {}
+
+    def get(self, key: str):
+        e = self.entries.get(key)
+        return None if e is None else dict(e["options"])
+
+    def put(self, key: str, options: dict, ms: float, default_ms: float) -> None:
+        self.entries[key] = {"options": dict(options), "ms": ms, "default_ms": default_ms}
+
+    def save(self) -> None:
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump({"version": self.version, "device": self.device, "entries": self.entries}, f, indent=1,
+                      sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def _device_name(device: int) -> str:
+    import torch
+
+    p = torch.cuda.get_device_properties(device)
+    return getattr(p, "gcnArchName", None) or p.name
+
+
+def _make_inputs(op: str, h: int, w: int, seed: int):
+    from . import synth
+
+    if op == "recon":
+        return synth.mr_inputs(h, w, seed=seed, n_disks=max(1, round(synth.MR_DISK_DENSITY * h * w)),
+                               radius=(5, 20), offset=32)
+    return synth.edt_input(h, w, seed=seed, coverage=0.3)
+
+
+def _timed(fn, reps: int) -> float:
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def tune_bucket(ctx: Context, op: str, conn: int, key: str, reps: int = 3, seed: int = 0) -> tuple:
+    """Time every candidate of GRID[op] on a synthetic image of bucket `key`.
+    Returns (best options, best ms, default ms).  Raises if any candidate's
+    output differs from the default options' output."""
+    import torch
+
+    h, w = bucket_side(key)
+    dev = torch.device("cuda", ctx.device)
+    saved = dict(ctx.options)
+    x = _make_inputs(op, h, w, seed)
+    if op == "recon":
+        J, I = (torch.from_numpy(a).to(dev) for a in x)
+        out = torch.empty_like(I)
+        fn = lambda: ctx.morph_recon(J, I, conn, out=out)
+        outs = [out]
+    else:
+        B = torch.from_numpy(x).to(dev)
+        sq = torch.empty(B.shape, dtype=torch.int32, device=dev)
+        nr = torch.empty_like(sq)
+        fn = lambda: ctx.edt(B, conn, out=(sq, nr))
+        outs = [sq, nr]
+    try:
+        ctx.set_options(**DEFAULTS)
+        default_ms = _timed(fn, reps)
+        ref = [o.clone() for o in outs]
+        best, best_ms = dict(DEFAULTS), default_ms
+        for cand in GRID[op]:
+            opts = dict(DEFAULTS, **cand)
+            ctx.set_options(**opts)
+            ms = _timed(fn, reps)
+            if not all(torch.equal(o, r) for o, r in zip(outs, ref)):
+                raise RuntimeError(f"tuning candidate {opts} changed the result of {key}")
+            if ms < best_ms:
+                best, best_ms = opts, ms
+        return best, best_ms, default_ms
+    finally:
+        ctx.set_options(**saved)
+
+
+def autotune(buckets, device: int = 0, cache_path: str | None = None, reps: int = 3, force: bool = False) -> TuneCache:
+    """Tune every (op, conn, pixels) of `buckets` that the cache lacks (all of
+    them with `force`) and save the cache."""
+    name = _device_name(device)
+    cache = TuneCache(cache_path or default_cache_path(name), name, _lib.load().iwpp_version())
+    ctx = Context(device)
+    try:
+        for op, conn, pixels in buckets:
+            key = bucket(op, conn, pixels)
+            if not force and cache.get(key) is not None:
+                continue
+            t = time.time()
+            opts, ms, dms = tune_bucket(ctx, op, conn, key, reps)
+            cache.put(key, opts, ms, dms)
+            print(f"[tune] {key}: {opts} {ms:.3f} ms (default {dms:.3f} ms, {time.time() - t:.1f}s)", flush=True)
+        cache.save()
+    finally:
+        ctx.close()
+    return cache
+
+
+class TunedContext(Context):
+    """A Context that sets the cached options of each call's bucket before the
+    call (the default options where the cache has no entry)."""
+
+    def __init__(self, device: int = 0, cache: TuneCache | None = None, **kw):
+        super().__init__(device, **kw)
+        if cache is None:
+            name = _device_name(device)
+            cache = TuneCache(default_cache_path(name), name, self._lib.iwpp_version())
+        self.cache = cache
+
+    def _apply(self, op: str, conn: int, pixels: int) -> None:
+        want = dict(DEFAULTS, **(self.cache.get(bucket(op, conn, pixels)) or {}))
+        if any(self.options.get(k) != v for k, v in want.items()):
+            self.set_options(**want)
+
+    def morph_recon(self, marker, mask, conn: int = 8, out=None):
+        self._apply("recon", conn, mask.numel())
+        return super().morph_recon(marker, mask, conn, out)
+
+    def edt(self, binary, conn: int = 8, out=None):
+        self._apply("edt", conn, binary.numel())
+        return super().edt(binary, conn, out)
