@@ -53,18 +53,15 @@ def kernel_source_sha() -> str:
 
 def algorithmic_bytes(part: str, kernel: str, n: int, q_ref: int, conn: int) -> float:
     """Bytes the method itself moves, attributed to the kernel that does that
-    part of the work.  Reconstruction: the raster and anti-raster passes read I
-    and J and write J (6 B/px, done by the seed pass) and every queue item moves
-    10 + 2*conn bytes (done by propagation; detection is folded into the
-    anti-raster pass in Algorithm 2 and gets no bytes).  EDT: initialisation
-    reads the input and writes the state (5 B/px); the rounds move 24 + 4*conn
-    bytes per frontier item and the finalisation reads the state and writes two
-    int32 maps (12 B/px)."""
+    part of the work.  Reconstruction (one persistent kernel whose round 0 is
+    the seed pass): the raster and anti-raster passes read I and J and write J
+    (6 B/px) and every queue item moves 10 + 2*conn bytes.  EDT:
+    initialisation reads the input and writes the state (5 B/px); the rounds
+    move 24 + 4*conn bytes per frontier item and the finalisation reads the
+    state and writes two int32 maps (12 B/px)."""
     if part.startswith("mr"):
-        if kernel == "mr_seed":
-            return 6.0 * n
         if kernel == "mr_propagate":
-            return float(10 + 2 * conn) * q_ref
+            return 6.0 * n + float(10 + 2 * conn) * q_ref
         return 0.0
     if kernel == "edt_init":
         return 5.0 * n
@@ -89,6 +86,108 @@ def _oracle_tile(args):
         return bool(np.array_equal(oracle.mr_fh(x[0], x[1], spec["conn"]), got[0]))
     s, n = oracle.edt_rounds(x, spec["conn"])
     return bool(np.array_equal(s, got[0]) and np.array_equal(n, got[1]))
+
+
+SERVE_POOL = 64
+
+
+def _gen_serve(i):
+    from paper_1209_3314_amd import synth
+
+    return synth.tile_inputs(synth.serve_pool(SERVE_POOL)[i])
+
+
+def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dict:
+    """Serving (iwpp_server_*): requests with host buffers (pinned), admitted
+    by a 64 GiB device budget, continuous batching ("batched") against the
+    same loop launching one job at a time ("plain").  Per rate: open-loop
+    Poisson arrivals for `seconds`, each request one of a pool of SERVE_POOL
+    tiles (square sides lognormal around 1024, clipped to [256, 8192], 70%
+    reconstruction, 30% EDT, conn 8); latency = end of the output download
+    minus the scheduled arrival.  Capacity: `burst` requests submitted at
+    once, pixels over the time until the last completes.  Every output is
+    compared with a plain single-image call of the same tile."""
+    from paper_1209_3314_amd import synth
+
+    specs = synth.serve_pool(SERVE_POOL)
+    host = gen.get()
+    dev = torch.device("cuda", 0)
+    jobs, ref, npx = [], [], []
+    for spec, x in zip(specs, host):
+        h, w = spec["h"], spec["w"]
+        npx.append(h * w)
+        if spec["op"] == "mr":
+            j = {"op": "recon", "conn": spec["conn"], "marker": torch.from_numpy(x[0]).pin_memory(),
+                 "mask": torch.from_numpy(x[1]).pin_memory(), "out": torch.empty((h, w), dtype=torch.uint8).pin_memory()}
+            ref.append([ctx.morph_recon(j["marker"].to(dev), j["mask"].to(dev), j["conn"]).cpu()])
+        else:
+            j = {"op": "edt", "conn": spec["conn"], "binary": torch.from_numpy(x).pin_memory(),
+                 "sqdist": torch.empty((h, w), dtype=torch.int32).pin_memory(),
+                 "nearest": torch.empty((h, w), dtype=torch.int32).pin_memory()}
+            sq, nr = ctx.edt(j["binary"].to(dev), j["conn"])
+            ref.append([sq.cpu(), nr.cpu()])
+        jobs.append(j)
+    outs = lambda j: [j["out"]] if j["op"] == "recon" else [j["sqdist"], j["nearest"]]
+
+    def clear():
+        for j in jobs:
+            for o in outs(j):
+                o.fill_(-7 if o.dtype == torch.int32 else 7)
+
+    def run(max_batch, arrivals):
+        """Submit (time_s, index) on schedule; returns per-request latency (ms),
+        makespan (s) and server statistics."""
+        clear()
+        with iw.Server(ctx, hbm_budget_bytes=64 << 30, max_batch=max_batch) as srv:
+            for j in jobs[:8]:  # warm-up
+                srv.submit(j)
+            srv.drain(timeout_ms=120000)
+            t0 = time.monotonic_ns() + 20_000_000
+            tickets = []
+            for t, idx in arrivals:
+                at = t0 + int(t * 1e9)
+                while True:
+                    now = time.monotonic_ns()
+                    if now >= at:
+                        break
+                    if at - now > 300_000:
+                        time.sleep((at - now - 200_000) / 1e9)
+                tickets.append((srv.submit(jobs[idx], arrival_ns=at), at))
+            srv.drain(timeout_ms=600000)
+            lat = np.array([srv.poll(tk)[1] for tk, _ in tickets])
+            st = srv.stats()
+        end = max(at + l * 1e6 for (_, at), l in zip(tickets, lat))
+        used = sorted(set(i for _, i in arrivals))
+        exact = all(torch.equal(o, r) for i in used for o, r in zip(outs(jobs[i]), ref[i]))
+        return lat, (end - t0) / 1e9, st, exact
+
+    def summary(arrivals, lat, span, st, exact):
+        px = sum(npx[i] for _, i in arrivals)
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3), "req_s": round(len(arrivals) / span, 1),
+                "mpix_s": round(px / span / 1e6, 1), "batches": st["batches"], "max_batch_jobs": st["max_batch_jobs"],
+                "peak_gib": round(st["peak_bytes"] / 2**30, 2), "failed": st["failed"], "equal_to_plain_calls": exact}
+
+    res = {"workload": f"{SERVE_POOL}-tile pool: square sides lognormal(median 1024, sigma 0.7) clipped [256, 8192], "
+                       "70% reconstruction / 30% EDT, conn 8; Poisson arrivals; host buffers pinned; 64 GiB budget",
+           "pool_mpix": round(sum(npx) / 1e6, 1), "rates": []}
+    for rate in rates:
+        arr = synth.serve_arrivals(rate, seconds, SERVE_POOL)
+        row = {"rate_req_s": rate, "seconds": seconds, "requests": len(arr)}
+        for mode, mb in (("batched", 0), ("plain", 1)):
+            row[mode] = summary(arr, *run(mb, arr))
+            log(f"serve rate {rate} {mode}: {row[mode]}")
+        row["p99_plain_over_batched"] = round(row["plain"]["p99_ms"] / max(row["batched"]["p99_ms"], 1e-9), 3)
+        res["rates"].append(row)
+    if burst:
+        arr = [(0.0, i % SERVE_POOL) for i in range(burst)]
+        cap = {"requests": burst}
+        for mode, mb in (("batched", 0), ("plain", 1)):
+            cap[mode] = summary(arr, *run(mb, arr))
+            log(f"serve burst {mode}: {cap[mode]}")
+        cap["throughput_batched_over_plain"] = round(cap["batched"]["mpix_s"] / max(cap["plain"]["mpix_s"], 1e-9), 3)
+        res["capacity"] = cap
+    return res
 
 
 def pool_workers() -> int:
@@ -215,6 +314,10 @@ def main():
                     help="skip the oracle run (then no bit-exactness check and no work counts)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tile batched leg")
     ap.add_argument("--batch-tiles", type=int, default=256, help="tiles in the batched leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-rates", default="800", help="comma-separated request rates (per second)")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="trace length per rate")
+    ap.add_argument("--serve-burst", type=int, default=256, help="requests of the capacity burst (0 = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -244,6 +347,13 @@ def main():
 
         pool = get_context("fork").Pool(pool_workers())
         gen = pool.map_async(_gen_tile, range(args.batch_tiles), chunksize=1)
+    serve_gen = None
+    if not args.no_serve:
+        from multiprocessing import get_context
+
+        if pool is None:
+            pool = get_context("fork").Pool(pool_workers())
+        serve_gen = pool.map_async(_gen_serve, range(SERVE_POOL), chunksize=1)
 
     import numpy as np
     import torch
@@ -299,7 +409,7 @@ def main():
     # Per-kernel averages, by part of the step (launch order within a step).
     per_call = []
     for name, conn in parts:
-        names = ["reset", "mr_seed", "mr_detect", "mr_propagate"] if name.startswith("mr") else ["reset", "edt_init", "edt_rounds"]
+        names = ["reset", "mr_propagate"] if name.startswith("mr") else ["reset", "edt_init", "edt_rounds"]
         per_call.append((name, conn, names))
     launches_per_step = sum(len(c[2]) for c in per_call)
     assert len(records) == launches_per_step * args.steps, (len(records), launches_per_step)
@@ -367,6 +477,11 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_leg(ctx, torch, np, pool, gen, args.batch_tiles, check=not args.no_cpu_baseline)
+    serve = None
+    if not args.no_serve:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        serve = serve_leg(ctx, iw, torch, np, serve_gen, rates, args.serve_seconds, args.serve_burst)
+    if pool is not None:
         pool.close()
         pool.join()
 
@@ -384,6 +499,7 @@ def main():
         "wall_ms_per_step": round(wall_ms / args.steps, 4),
         "work": {"q_ref": q_ref, "gpu": gpu_stats},
         "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
 

@@ -81,7 +81,7 @@ typedef struct {
 typedef struct {
   int32_t status;            /* IWPP_OK, or IWPP_EDEVICE if a kernel hit a safety limit */
   int32_t op;                /* 1 = reconstruction, 2 = distance transform, 3 = batch */
-  int64_t seeds;             /* MR: pixels meeting the seed condition of Alg. 5 after the seed pass;
+  int64_t seeds;             /* MR: tiles the seed pass left to propagation (visited in round 1);
                                 EDT: contour features (initial frontier) */
   int64_t items;             /* MR: tile visits in propagation; EDT: frontier items over all rounds */
   int64_t sweeps;            /* MR: sweep iterations over all tile visits */
@@ -99,9 +99,9 @@ typedef struct {
 
 enum {
   IWPP_K_RESET = 0,        /* counter reset at the start of every call */
-  IWPP_K_MR_SEED = 1,      /* reconstruction seed pass (tile sweeps) */
-  IWPP_K_MR_DETECT = 2,    /* reconstruction seed detection */
-  IWPP_K_MR_PROPAGATE = 3, /* reconstruction persistent propagation */
+  IWPP_K_MR_SEED = 1,      /* reserved (the seed pass is round 0 of IWPP_K_MR_PROPAGATE) */
+  IWPP_K_MR_DETECT = 2,    /* reserved (no separate seed detection) */
+  IWPP_K_MR_PROPAGATE = 3, /* reconstruction: persistent kernel, seed pass + propagation */
   IWPP_K_EDT_INIT = 4,     /* distance transform initialisation */
   IWPP_K_EDT_ROUNDS = 5    /* distance transform rounds + finalisation */
 };

@@ -105,8 +105,8 @@ DeviceGuard::~DeviceGuard() {
 }
 
 size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
-  const uint64_t t = op == IWPP_OP_RECON ? (uint64_t)((h + 63) / 64) * (uint64_t)((w + 63) / 64)
-                                         : (uint64_t)((h + 31) / 32) * (uint64_t)((w + 31) / 32);
+  const int ts = op == IWPP_OP_RECON ? iwpp::kMrTile : iwpp::kEdtTile;
+  const uint64_t t = (uint64_t)((h + ts - 1) / ts) * (uint64_t)((w + ts - 1) / ts);
   const uint64_t np = (uint64_t)h * (uint64_t)w;
   // 5 tile words (+ alignment slack of the per-group arrays is added by the caller)
   return (size_t)(20 * t + (op == IWPP_OP_EDT ? 8 * np : 0) + (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
@@ -120,15 +120,15 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
 // ---- plans ---------------------------------------------------------------------
 
 void mr_place(iwpp::MrJob& m, uint64_t& tiles) {
-  m.tiles_y = (m.h + 63) / 64;
-  m.tiles_x = (m.w + 63) / 64;
+  m.tiles_y = (m.h + iwpp::kMrTile - 1) / iwpp::kMrTile;
+  m.tiles_x = (m.w + iwpp::kMrTile - 1) / iwpp::kMrTile;
   m.tile_base = (uint32_t)tiles;
   tiles += (uint64_t)m.tiles_y * (uint64_t)m.tiles_x;
 }
 
 void edt_place(iwpp::EdtJob& e, uint64_t& pix, uint64_t& tiles) {
-  e.tiles_y = (e.h + 31) / 32;
-  e.tiles_x = (e.w + 31) / 32;
+  e.tiles_y = (e.h + iwpp::kEdtTile - 1) / iwpp::kEdtTile;
+  e.tiles_x = (e.w + iwpp::kEdtTile - 1) / iwpp::kEdtTile;
   e.tile_base = (uint32_t)tiles;
   e.pix_base = pix;
   tiles += (uint64_t)e.tiles_y * (uint64_t)e.tiles_x;

@@ -97,32 +97,48 @@ __device__ __forceinline__ void stat_add(unsigned long long* stats, int field, u
 // Counters sit 256 bytes apart so they do not share a cache line.  Every wait
 // is bounded: on timeout (or when another workgroup raised `abort`) the
 // barrier returns false and the caller must leave the kernel.
+//
+// The barrier can also OR one flag per workgroup over the grid: an arrival
+// adds 1 to the low half of its counter and, when the flag is set, 1 to the
+// high half, so the last arrival of a group knows the group's OR and passes it
+// on to the top counter, whose last arrival publishes the grid's OR before it
+// bumps the generation.  No other word is written, so a grid-wide "did anyone
+// do X" costs nothing beyond the barrier.
 struct GridBarrier {
   uint32_t group[8][64];
   uint32_t top[64];
   uint32_t gen[64];
   uint32_t abort[64];
+  uint32_t result[64];
 };
 
 constexpr uint32_t kSpinLimit = 1u << 24;  // ~ seconds of polling, far beyond any real wait
+constexpr uint32_t kArriveFlag = 1u << 16;  // an arrival's flag in the high half of a counter
 
-__device__ __forceinline__ bool grid_barrier(GridBarrier* b, uint32_t& gen, unsigned long long* stats) {
-  __shared__ uint32_t ok;
+// `flag` (LDS word, or null) is read after every wave of the workgroup has
+// arrived and is reset to 0; the grid's OR of it is returned in `any`.
+__device__ __forceinline__ bool grid_barrier_or(GridBarrier* b, uint32_t& gen, unsigned long long* stats,
+                                                uint32_t* flag, bool& any) {
+  __shared__ uint32_t ok, anyv;
   __syncthreads();
   if (threadIdx.x == 0) {
     drain();
+    const bool mine = flag != nullptr && *flag != 0u;
+    if (flag) *flag = 0u;
     const uint32_t nwg = gridDim.x;
     const uint32_t g = blockIdx.x & 7u;
     const uint32_t in_group = (nwg - g + 7u) >> 3;
     const uint32_t groups = nwg < 8u ? nwg : 8u;
     uint32_t res = 1;
-    uint32_t old = atomic_add(&b->group[g][0], 1u);
-    if (old == in_group - 1) {
+    const uint32_t old = atomic_add(&b->group[g][0], 1u + (mine ? kArriveFlag : 0u));
+    if ((old & (kArriveFlag - 1u)) == in_group - 1) {
+      const bool gany = mine || (old >> 16) != 0u;
       cstore(&b->group[g][0], 0u);
       drain();
-      uint32_t old2 = atomic_add(&b->top[0], 1u);
-      if (old2 == groups - 1) {
+      const uint32_t old2 = atomic_add(&b->top[0], 1u + (gany ? kArriveFlag : 0u));
+      if ((old2 & (kArriveFlag - 1u)) == groups - 1) {
         cstore(&b->top[0], 0u);
+        cstore(&b->result[0], (gany || (old2 >> 16) != 0u) ? 1u : 0u);
         drain();
         cstore(&b->gen[0], gen + 1);
       }
@@ -140,9 +156,16 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, uint32_t& gen, unsi
     }
     gen += 1;
     ok = res;
+    anyv = res ? cload(&b->result[0]) : 0u;
   }
   __syncthreads();
+  any = anyv != 0u;
   return ok != 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(GridBarrier* b, uint32_t& gen, unsigned long long* stats) {
+  bool unused;
+  return grid_barrier_or(b, gen, stats, nullptr, unused);
 }
 
 // Compiler + memory ordering point for lanes of one wave that exchange data

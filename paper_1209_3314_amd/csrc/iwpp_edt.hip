@@ -16,31 +16,51 @@
 // whose pixels or one-pixel halo changed in the previous round: one wave loads
 // the tile and its halo from the previous round's buffer into LDS, recomputes
 // every pixel of the tile with the operator above, writes the tile to the other
-// buffer, and lists itself and the neighbouring tiles its changes can reach for
+// buffer, and flags itself and the neighbouring tiles its changes can reach for
 // the next round.  Nothing writes the buffer a round reads, so no atomics touch
 // pixels.  A tile that is not visited in a round keeps equal values in both
 // buffers: a tile changes only in rounds it is visited, and after a round in
 // which it changed it is visited again, so it stops being visited only after a
-// round in which it (re)wrote its unchanged values.
+// round in which it (re)wrote its unchanged values.  The frontier of tiles is
+// a dense array of per-tile flags, set by plain stores and cleared by the wave
+// that visits the tile; every wave scans its own share of it each round, so
+// building the frontier needs no counter and no atomic.
 //
-// State is the feature's packed coordinates (y << 16 | x), 4 bytes per pixel;
-// squared distances are recomputed exactly in integers.
+// State is the feature's packed coordinates (y << 16 | x), 4 bytes per pixel.
+// A candidate's squared distance is one saturating packed 16-bit subtraction
+// and one 2-term dot product; "none" is the packed pair (-32768, -32768),
+// whose saturated distance exceeds that of any real feature (coordinates are
+// below 32767), and whose packed value exceeds any real feature's, so the
+// lexicographic minimum needs no special case for it.
 #include "iwpp_device.hpp"
 #include "iwpp_internal.hpp"
 
 namespace iwpp {
 namespace edt {
 
-constexpr int TE = 32;            // tile side
+constexpr int TE = kEdtTile;      // tile side
 constexpr int RP = TE + 2;        // region side with the halo
 constexpr int kWavesPerBlock = 4;
-constexpr int kStageCap = 128;
-constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kNone = 0x80008000u;
 constexpr uint32_t kMaxRounds = 1u << 20;
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef short s2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pack_yx(int y, int x) { return ((uint32_t)y << 16) | (uint32_t)x; }
+
+// Squared distance between packed points q and f (0 <= coordinates < 32767
+// for q; f real or kNone).
+__device__ __forceinline__ uint32_t d2(uint32_t q, uint32_t f) {
+  const s2 e = __builtin_elementwise_sub_sat(__builtin_bit_cast(s2, q), __builtin_bit_cast(s2, f));
+  return (uint32_t)__builtin_amdgcn_sdot2(e, e, 0, false);
+}
+
+// Offer candidate f to the best (distance << 32 | feature) key of pixel q.
+__device__ __forceinline__ void offer(uint32_t q, uint32_t f, unsigned long long& best) {
+  const unsigned long long key = ((unsigned long long)d2(q, f) << 32) | f;
+  best = key < best ? key : best;
+}
 
 struct TileRef {
   EdtJob j;
@@ -123,20 +143,21 @@ __device__ uint32_t relax_tile(const WaveLds& L, uint32_t* dst, const TileRef& t
   for (int k = 0; k < TE / 2; ++k) {
     const int y = yb + 2 * k;
     const int qy = y0 + y;
-    const uint32_t old = L.F[(y + 1) * RP + x + 1];
-    uint32_t bd = 0xFFFFFFFFu, bf = kNone;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (CONN == 4 && dy != 0 && dx != 0) continue;
-        const uint32_t f = L.F[(y + 1 + dy) * RP + x + 1 + dx];
-        const int ey = qy - (int)(f >> 16), ex = qx - (int)(f & 0xffffu);
-        const uint32_t d = (uint32_t)(ey * ey + ex * ex);
-        const bool take = f != kNone && (d < bd || (d == bd && f < bf));
-        bd = take ? d : bd;
-        bf = take ? f : bf;
-      }
+    const uint32_t q = pack_yx(qy, qx);
+    const uint32_t* c = &L.F[(y + 1) * RP + x + 1];
+    const uint32_t old = c[0];
+    unsigned long long best = ((unsigned long long)d2(q, old) << 32) | old;
+    offer(q, c[-RP], best);
+    offer(q, c[RP], best);
+    offer(q, c[-1], best);
+    offer(q, c[1], best);
+    if (CONN == 8) {
+      offer(q, c[-RP - 1], best);
+      offer(q, c[-RP + 1], best);
+      offer(q, c[RP - 1], best);
+      offer(q, c[RP + 1], best);
+    }
+    const uint32_t bf = (uint32_t)best;
     const bool inside = qy < j.h && qx < j.w;
     if (inside)
       __builtin_amdgcn_raw_buffer_store_b32(bf, rs, ((uint32_t)(qy - row0) * (uint32_t)j.w + (uint32_t)qx) * 4u, 0, kSc1);
@@ -161,133 +182,145 @@ __device__ uint32_t relax_tile(const WaveLds& L, uint32_t* dst, const TileRef& t
   return m;
 }
 
-// Put tile t on the list of parity `par` (lanes with pred), once per round.
-__device__ __forceinline__ void mark_tiles(const EdtArgs& a, WaveStage& s, bool pred, uint32_t t, int par,
-                                           uint32_t* count) {
-  bool fresh = false;
-  if (pred) fresh = atomic_or(a.flags + (size_t)par * a.ntiles + t, 1u) == 0u;
-  stage_append(s, fresh, t, a.lists + (size_t)par * a.ntiles, count, a.ntiles, a.ovf);
-}
-
-// List the tiles that the changes of tile tr (mask m from relax_tile) reach:
-// itself and every neighbour whose halo holds a changed pixel.
-__device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const TileRef& tr, uint32_t m, int par,
-                                           uint32_t* count) {
+// Flag, for the round of parity `par`, the tiles that the changes of tile tr
+// (mask m of relax_tile, or of the initial state) reach: itself (bit 0) and
+// each neighbour whose halo holds a changed pixel.  Lanes 0..8 of the wave
+// each handle one candidate.  Returns (wave-uniform) whether any tile was
+// flagged.
+__device__ __forceinline__ bool flag_reach(const EdtArgs& a, const TileRef& tr, uint32_t m, int par) {
   const int l = lane();
   int dy = 0, dx = 0;
   bool want = false;
   if (l == 0) {
     want = (m & 1u) != 0u;
-  } else if (l < 9) {
+  } else if (l <= 8) {
     // lanes 1..8: top, bottom, left, right, top-left, top-right, bottom-left, bottom-right
     const int k = l - 1;
-    const uint32_t bit = k < 4 ? (2u << k) : (32u << (k - 4));
-    want = (m & bit) != 0u;
+    want = (m & (k < 4 ? (2u << k) : (32u << (k - 4)))) != 0u;
     dy = k == 0 ? -1 : (k == 1 ? 1 : (k < 4 ? 0 : (k < 6 ? -1 : 1)));
     dx = k < 2 ? 0 : (k == 2 ? -1 : (k == 3 ? 1 : ((k & 1) ? 1 : -1)));
   }
   const int ny = tr.ty + dy, nx = tr.tx + dx;
   want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
-  mark_tiles(a, s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), par, count);
+  if (want) cstore(a.flags + (size_t)par * a.ntiles + tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), 1u);
+  return ballot(want) != 0u;
 }
 
 // Initial state (features carry themselves, everything else none) in both
 // buffers, the contour-feature count (Algorithm 6's initial queue), and the
-// first round's list: the tiles holding a non-feature pixel next to a feature,
-// which are exactly the pixels round 1 can change.  One wave per tile.
+// first round's flags: the tiles holding a non-feature pixel next to a
+// feature (exactly the pixels round 1 changes) and the neighbours whose halo
+// holds one.  One wave per tile; the binary region is staged in LDS.  The
+// flags must be zero beforehand.
 template <int CONN>
 __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  constexpr int BP = RP + 2;  // byte pitch
+  __shared__ uint8_t binl[kWavesPerBlock][RP * BP];
   const int w = threadIdx.x / kWave;
   const uint32_t t = blockIdx.x * kWavesPerBlock + w;
   if (t >= a.ntiles) return;
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const TileRef tr = tile_ref(a, t);
   const EdtJob& j = tr.j;
-  const int x = lane() & (TE - 1), yb = lane() >> 5;
-  const int qx = tr.tx * TE + x;
-  uint32_t contour = 0;
-  bool reach = false;
-  if (lane() == 0) {
-    a.flags[t] = 0u;
-    a.flags[a.ntiles + t] = 0u;
+  const int y0 = tr.ty * TE, x0 = tr.tx * TE;
+  uint8_t* B = binl[w];
+  // Region bytes: 1 = feature, 0 = other or outside the image.
+  for (int idx = lane(); idx < RP * RP; idx += kWave) {
+    const int ry = idx / RP, rx = idx - ry * RP;
+    const int y = y0 - 1 + ry, x = x0 - 1 + rx;
+    B[ry * BP + rx] = (y >= 0 && y < j.h && x >= 0 && x < j.w && j.bin[(size_t)y * (uint32_t)j.w + (uint32_t)x] == 0) ? 1 : 0;
   }
+  wave_sync();
+  const int x = lane() & (TE - 1), yb = lane() >> 5;
+  const int qx = x0 + x;
+  uint32_t contour = 0, any = 0;
   for (int k = 0; k < TE / 2; ++k) {
-    const int qy = tr.ty * TE + yb + 2 * k;
+    const int y = yb + 2 * k;
+    const int qy = y0 + y;
     if (qy >= j.h || qx >= j.w) continue;
-    const uint32_t p = (uint32_t)qy * (uint32_t)j.w + (uint32_t)qx;
-    const bool feat = j.bin[p] == 0;
-    bool nb_feat = false, nb_other = false;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        if ((dy == 0 && dx == 0) || (CONN == 4 && dy != 0 && dx != 0)) continue;
-        const int ny = qy + dy, nx = qx + dx;
-        if (ny < 0 || ny >= j.h || nx < 0 || nx >= j.w) continue;
-        const bool f = j.bin[(uint32_t)ny * (uint32_t)j.w + (uint32_t)nx] == 0;
-        nb_feat |= f;
-        nb_other |= !f;
-      }
+    const uint8_t* c = &B[(y + 1) * BP + x + 1];
+    const bool feat = c[0] != 0;
+    int nf = c[-BP] + c[BP] + c[-1] + c[1];
+    int nin = (qy > 0) + (qy + 1 < j.h) + (qx > 0) + (qx + 1 < j.w);
+    if (CONN == 8) {
+      nf += c[-BP - 1] + c[-BP + 1] + c[BP - 1] + c[BP + 1];
+      nin += (qy > 0 && qx > 0) + (qy > 0 && qx + 1 < j.w) + (qy + 1 < j.h && qx > 0) + (qy + 1 < j.h && qx + 1 < j.w);
+    }
     const uint32_t v = feat ? pack_yx(qy, qx) : kNone;
-    a.feat0[j.pix_base + p] = v;
-    a.feat1[j.pix_base + p] = v;
-    contour += (feat && nb_other) ? 1u : 0u;
-    reach |= !feat && nb_feat;
+    const size_t p = j.pix_base + (size_t)qy * (uint32_t)j.w + (uint32_t)qx;
+    a.feat0[p] = v;
+    a.feat1[p] = v;
+    contour += (feat && nf < nin) ? 1u : 0u;  // a feature with a non-feature neighbour
+    if (!feat && nf > 0) {
+      any |= 1u;
+      if (y == 0) any |= 2u;
+      if (y == TE - 1) any |= 4u;
+      if (x == 0) any |= 8u;
+      if (x == TE - 1) any |= 16u;
+      if (y == 0 && x == 0) any |= 32u;
+      if (y == 0 && x == TE - 1) any |= 64u;
+      if (y == TE - 1 && x == 0) any |= 128u;
+      if (y == TE - 1 && x == TE - 1) any |= 256u;
+    }
   }
   uint32_t tot = contour;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < 9; ++b)
+    if (ballot((any >> b) & 1u)) m |= 1u << b;
   if (lane() == 0) {
     stat_add(a.stats, kStatSeeds, tot);
     stat_add(a.stats, kStatItems, tot);  // the first frontier
   }
-  // round 1 reads list parity 1 with count slot 1 (the vote needs every lane)
-  const bool listed = ballot(reach) != 0;
-  mark_tiles(a, s, lane() == 0 && listed, t, 1, a.counts + 64);
-  stage_flush(s, a.lists + a.ntiles, a.counts + 64, a.ntiles, a.ovf);
+  (void)flag_reach(a, tr, m, 1);  // round 1 reads parity 1
 }
 
 template <int CONN>
 __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
-  __shared__ uint32_t nshared;
-  const int w = threadIdx.x / kWave;
+  __shared__ uint32_t flagged;  // this workgroup flagged a tile in this round
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
-  const uint32_t gw = blockIdx.x * kWavesPerBlock + w, nw = gridDim.x * kWavesPerBlock;
+  const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
+  if (threadIdx.x == 0) flagged = 0u;
   uint32_t gen = 0;
   unsigned long long changed = 0, visits = 0;
-  uint32_t r = 1;
-  for (;; ++r) {
-    if (threadIdx.x == 0) nshared = cload(a.counts + (r % 3u) * 64u);
-    __syncthreads();
-    uint32_t n = nshared;
-    if (n == 0u) break;
+  uint32_t rounds = 0;
+  for (uint32_t r = 1;; ++r) {
     if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
     }
-    if (n > a.ntiles) n = a.ntiles;
-    if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
     const uint32_t* rd = (r & 1u) ? a.feat0 : a.feat1;  // buffer (r-1)&1
     uint32_t* wr = (r & 1u) ? a.feat1 : a.feat0;        // buffer r&1
     const int par = (int)(r & 1u), npar = 1 - par;
-    const uint32_t* list = a.lists + (size_t)par * a.ntiles;
-    uint32_t* ncount = a.counts + ((r + 1u) % 3u) * 64u;
-    for (uint32_t i = gw; i < n; i += nw) {
-      const uint32_t t = cload(list + i);
-      if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
-      const TileRef tr = tile_ref(a, t);
-      load_region(rd, tr, L);
-      uint32_t c = 0;
-      const uint32_t m = relax_tile<CONN>(L, wr, tr, c);
-      changed += c;
-      visits++;
-      mark_reach(a, s, tr, m, npar, ncount);
+    uint32_t* flg = a.flags + (size_t)par * a.ntiles;
+    // This wave's share of the tiles: gw, gw + nw, gw + 2 nw, ...
+    for (uint32_t base = gw; base < a.ntiles; base += nw * (uint32_t)kWave) {
+      const uint32_t mine = base + (uint32_t)lane() * nw;
+      uint64_t mm = ballot(mine < a.ntiles && cload(flg + mine) != 0u);
+      while (mm) {
+        const int b = __ffsll((long long)mm) - 1;
+        mm &= mm - 1;
+        const uint32_t t = base + (uint32_t)b * nw;
+        if (lane() == 0) cstore(flg + t, 0u);
+        const TileRef tr = tile_ref(a, t);
+        load_region(rd, tr, L);
+        uint32_t c = 0;
+        const uint32_t m = relax_tile<CONN>(L, wr, tr, c);
+        changed += c;
+        visits++;
+        if (flag_reach(a, tr, m, npar) && lane() == 0) flagged = 1u;
+        wave_sync();  // LDS is reloaded by the next visit
+      }
     }
-    stage_flush(s, a.lists + (size_t)npar * a.ntiles, ncount, a.ntiles, a.ovf);
-    if (!grid_barrier(a.bar, gen, a.stats)) return;
+    // The barrier also tells whether any workgroup flagged a tile for round r+1.
+    bool more = false;
+    if (!grid_barrier_or(a.bar, gen, a.stats, &flagged, more)) return;
+    if (!more) {
+      rounds = r - 1;  // round r changed nothing; rounds 1..r-1 did
+      break;
+    }
   }
   // Both buffers now agree everywhere; write the outputs.
   const uint32_t* fin = a.feat0;
@@ -301,9 +334,8 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
         j.sqdist[p] = -1;
         j.nearest[p] = -1;
       } else {
-        const int y = (int)(p / (uint32_t)j.w), x = (int)(p - (uint32_t)y * (uint32_t)j.w);
-        const int ey = y - (int)(f >> 16), ex = x - (int)(f & 0xffffu);
-        j.sqdist[p] = ey * ey + ex * ex;
+        const uint32_t y = p / (uint32_t)j.w, x = p - y * (uint32_t)j.w;
+        j.sqdist[p] = (int32_t)d2(pack_yx((int)y, (int)x), f);
         j.nearest[p] = (int32_t)((f >> 16) * (uint32_t)j.w + (f & 0xffffu));
       }
     }
@@ -314,7 +346,7 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
     stat_add(a.stats, kStatUpdates, changed);
     stat_add(a.stats, kStatSweeps, visits);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatRounds, r >= 2u ? r - 2u : 0u);
+  if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatRounds, rounds);
 }
 
 // Image of every global tile, by binary search over the images' first tiles.
@@ -340,6 +372,10 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
       *err = "tile map launch failed";
       return -1;
     }
+  }
+  if (zero_words(a.flags, 2ull * a.ntiles, stream) != 0) {
+    *err = "flag reset launch failed";
+    return -1;
   }
   const uint32_t init_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   rec->begin(4, stream);
@@ -377,7 +413,7 @@ uint32_t persistent_grid(const void* fn, int per_cu, int cus) {
   hipFuncAttributes fa{};
   int lim = per_cu < 4 ? per_cu : 4;
   if (hipFuncGetAttributes(&fa, fn) == hipSuccess && fa.sharedSizeBytes > 0) {
-    const int by_lds = (int)((128u * 1024u) / (unsigned)fa.sharedSizeBytes);
+    const int by_lds = (int)((160u * 1024u) / (unsigned)fa.sharedSizeBytes);  // LDS per CU
     if (by_lds < lim) lim = by_lds;
   }
   if (lim < 1) lim = 1;

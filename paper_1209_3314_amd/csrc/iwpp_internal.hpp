@@ -8,6 +8,10 @@ namespace iwpp {
 
 struct GridBarrier;
 
+// Tile geometry shared by the host plans and the kernels.
+constexpr int kMrTile = 64;   // reconstruction tiles: 64 x 64 pixels
+constexpr int kEdtTile = 32;  // EDT tiles: 32 x 32 pixels
+
 // One reconstruction image of a launch.
 struct MrJob {
   const uint8_t* marker;
@@ -44,7 +48,7 @@ struct EdtJob {
   int32_t* sqdist;
   int32_t* nearest;
   int32_t h, w;
-  int32_t tiles_y, tiles_x;  // 32x32 tiles
+  int32_t tiles_y, tiles_x;  // kEdtTile x kEdtTile tiles
   uint32_t tile_base;        // first global tile id of this image
   uint32_t pad;
   unsigned long long pix_base;  // first global pixel id of this image
@@ -61,10 +65,10 @@ struct EdtArgs {
   unsigned long long npix;    // total pixels over all images
   uint32_t* feat0;            // [npix] nearest feature (y << 16 | x), ~0 = none; round parity 0
   uint32_t* feat1;            // [npix] round parity 1
-  uint32_t* flags;            // [2][ntiles] "already listed" per round parity
-  uint32_t* lists;            // [2][ntiles] active tiles per round parity
-  uint32_t* counts;           // [3][64]
-  uint32_t* ovf;              // [64] never set: a list holds each tile once
+  uint32_t* flags;            // [2][ntiles] tile to visit, per step parity
+  uint32_t* lists;            // unused (kept for the scratch layout)
+  uint32_t* counts;           // [3][64] "some tile is flagged" words of consecutive steps
+  uint32_t* ovf;              // unused
   GridBarrier* bar;
   unsigned long long* stats;
 };

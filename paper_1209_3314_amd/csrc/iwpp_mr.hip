@@ -5,27 +5,32 @@
 // so any schedule of valid updates that reaches stability gives identical
 // bytes (the paper's exactness argument for Algorithm 5, which does hold here).
 //
-// How (the steps of Algorithm 5, re-planned for CDNA4):
-//   1. seed pass   -- raster / anti-raster scans, split into row-wise and
-//                     column-wise sweeps as Algorithm 5 does, run per 64x64
-//                     tile in LDS and repeated until the tile is locally
-//                     stable (one wave per tile, lane = row or column);
-//   2. seed detect -- dense test of the full-neighbourhood seed condition of
-//                     Algorithm 5 on every pixel; a tile holding a pixel that a
-//                     neighbour can still raise goes on the first work list;
-//   3. propagation -- one persistent, cooperative kernel works off the list in
-//                     rounds (the queue swap of Algorithm 4): a wave loads a
-//                     listed tile with its one-pixel halo, sweeps it to local
-//                     stability, writes it back, and lists each neighbouring
-//                     tile whose border pixels it can still raise.  Work lists
-//                     are staged per wave in LDS and flushed with one atomic.
-//   4. overflow    -- a work list has a capacity (the paper's fixed-size
-//                     global queue, Sec. 3.2); an append past it is dropped and
-//                     flagged, and the next round rebuilds its list by a dense
-//                     seed detection over the current image, which is a valid
-//                     restart point because every intermediate image is
-//                     (Sec. 3.2: re-running from a partial output gives the same
-//                     answer).
+// How (the steps of Algorithm 5, re-planned for CDNA4).  One persistent,
+// cooperative kernel runs in rounds (the queue swap of Algorithm 4); a round
+// visits tiles, one wave per 64x64 tile held in LDS with a one-pixel halo:
+//   round 0  -- the seed pass: every tile is loaded from the marker (clamped
+//               to the mask) and swept with Algorithm 5's raster and
+//               anti-raster scans, split into row-wise and column-wise
+//               sweeps, until it is locally stable (lane = row or column);
+//   round r  -- each tile flagged in round r-1 is loaded from the current
+//               image, swept to local stability and written back.
+// After a visit the wave flags each neighbouring tile that a border change
+// can still raise (Algorithm 5's propagation condition, J(q) < J(p) and
+// J(q) < I(q), tested against the halo as loaded), and the tile itself if the
+// sweep cap stopped it.  This replaces Algorithm 5's dense seed detection: in
+// round 0 a halo pixel holds the neighbour's initial value, and a border pixel
+// that did not rise was seen with that same value by the neighbour's own
+// sweep, so only risen border pixels can leave a seed across a tile edge.
+//
+// The tile frontier is, by default, a dense array of per-tile flags set by
+// plain stores and scanned by every wave for its share, so building it needs
+// no counter or atomic.  With a capacity, it is instead a bounded work list
+// (the paper's fixed-size global queue, Sec. 3.2): appends are staged per
+// wave in LDS and flushed with one atomic; an append past the capacity is
+// dropped and flagged, and the next round becomes a full round that visits
+// every tile holding a raisable pixel of the current image, which is a valid
+// restart point because every intermediate image is (Sec. 3.2: re-running
+// from a partial output gives the same answer).
 //
 // The value updates are max-then-min of bytes; the per-tile state is owned by
 // exactly one wave at a time (a tile is on a round's list at most once), so no
@@ -38,11 +43,12 @@
 namespace iwpp {
 namespace mr {
 
-constexpr int T = 64;          // tile side: lanes map to the 64 columns (or rows)
+constexpr int T = kMrTile;     // tile side: lanes map to the 64 columns (or rows)
+static_assert(T == 64, "lanes map to tile rows and columns");
 constexpr int kRows = T + 2;   // region rows with the halo
-constexpr int P = 76;          // LDS row pitch: 19 dwords, so column walks hit distinct banks
+constexpr int P = 68;          // LDS row pitch: 17 dwords, so column walks hit distinct banks
 constexpr int kOff = 4;        // LDS byte offset of tile column 0 (4-byte aligned chunks)
-constexpr int kRegion = kRows * P;
+constexpr int kRegion = kRows * P + 4;  // the last row's column 64 spills into the pad
 constexpr int kWavesPerBlock = 4;
 constexpr int kStageCap = 128;
 constexpr uint32_t kMaxRounds = 1u << 20;
@@ -315,28 +321,7 @@ __device__ void list_tile(const MrArgs& a, uint32_t t, int par, uint32_t* count)
   }
 }
 
-// ---- seed pass --------------------------------------------------------------------
-// One wave per tile.  Also clears the work-list bookkeeping for this call.
-template <int CONN>
-__global__ __launch_bounds__(256, 4) void k_seed(MrArgs a) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const uint32_t t = blockIdx.x * kWavesPerBlock + w;
-  if (t >= a.ntiles) return;
-  if (lane() == 0) {
-    a.flags[t] = 0u;
-    a.flags[a.ntiles + t] = 0u;
-  }
-  const TileRef tr = tile_ref(a, t);
-  WaveLds& L = lds[w];
-  load_region<true>(tr, L);
-  uint32_t iters = 0;
-  sweep_tile<CONN>(L, a.seed_sweeps, iters);  // a tile left unsettled is found by the dense detection
-  store_tile(tr, L);
-  if (lane() == 0) stat_add(a.stats, kStatSweeps, iters);
-}
-
-// ---- seed detection -----------------------------------------------------------------
+// ---- raisable-pixel test (full rounds of the bounded mode) -------------------------
 // Dense test of the tile in LDS (region loaded with its halo).  Returns
 // (wave-uniform) whether some pixel q of the tile can still be raised by a
 // neighbour p, i.e. J(q) < J(p) and J(q) < I(q) -- Algorithm 5's propagation
@@ -429,34 +414,68 @@ __device__ __forceinline__ void mark_tiles(const MrArgs& a, WaveStage& s, bool p
   s.n += k;
 }
 
-template <int CONN>
-__global__ __launch_bounds__(256) void k_detect(MrArgs a) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const uint32_t t = blockIdx.x * kWavesPerBlock + w;
-  if (t >= a.ntiles) return;
-  const TileRef tr = tile_ref(a, t);
-  WaveLds& L = lds[w];
-  load_region<false>(tr, L);
-  uint32_t seeds = 0;
-  const bool dirty = lds_dirty<CONN>(L, seeds);
-  if (lane() == 0) {
-    stat_add(a.stats, kStatSeeds, seeds);
-    if (dirty) list_tile(a, t, 0, a.counts);
+// ---- persistent propagation -----------------------------------------------------------
+// Frontier marks.  Dense mode: a plain store of the tile's flag (whether a
+// round flagged anything travels with the grid barrier).  Bounded mode: a
+// staged list append.  Returns (wave-uniform) whether some lane marked.
+template <bool kBounded>
+__device__ __forceinline__ bool mark(const MrArgs& a, WaveStage& s, bool pred, uint32_t t, int par, uint32_t* word) {
+  if (kBounded) {
+    mark_tiles(a, s, pred, t, par, word);
+  } else if (pred) {
+    cstore(a.flags + (size_t)par * a.ntiles + t, 1u);
   }
+  return ballot(pred) != 0u;
 }
 
-// ---- persistent propagation -----------------------------------------------------------
-// One tile visit: load the tile and its halo, sweep to local stability, write
-// back, and list the neighbouring tiles a border change can raise (and the
-// tile itself if the sweep cap stopped it).  With `check`, a tile that has no
-// raisable pixel is left alone.
-template <int CONN>
-__device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t, bool check, int npar,
-                           uint32_t* ncount, uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
+// Flag the neighbours named by border mask m (see border_marks) and, if
+// `unsettled`, the tile itself, for the round of parity `par` (lanes 0..8).
+template <bool kBounded>
+__device__ bool mark_reach(const MrArgs& a, WaveStage& s, const TileRef& tr, uint32_t m, bool unsettled, int par,
+                           uint32_t* word) {
+  const int l = lane();
+  int dy = 0, dx = 0;
+  bool want = false;
+  if (l < 8) {
+    // bit order of border_marks: top, bottom, left, right, tl, tr, bl, br
+    want = (m >> l) & 1u;
+    dy = l < 2 ? (l == 0 ? -1 : 1) : (l < 4 ? 0 : (l < 6 ? -1 : 1));
+    dx = l < 2 ? 0 : (l < 4 ? (l == 2 ? -1 : 1) : ((l & 1) ? 1 : -1));
+  } else if (l == 8) {
+    want = unsettled;
+  }
+  const int ny = tr.ty + dy, nx = tr.tx + dx;
+  want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
+  return mark<kBounded>(a, s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), par, word);
+}
+
+// Round-0 visit: the seed pass of one tile (load from the clamped marker,
+// sweep, write back) and its marks for round 1.
+template <int CONN, bool kBounded>
+__device__ bool seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t, uint32_t* word, uint32_t& iters) {
+  const TileRef tr = tile_ref(a, t);
+  load_region<true>(tr, L);
+  const int l = lane();
+  const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
+  const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
+  uint32_t it = 0;
+  const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it);
+  iters += it;
+  store_tile(tr, L);
+  const uint32_t m = border_marks<CONN>(L, ot, ob, ol, orr);
+  return mark_reach<kBounded>(a, s, tr, m, !stable, 1, word);
+}
+
+// One propagation visit: load the tile and its halo, sweep to local
+// stability, write back, and flag the neighbouring tiles a border change can
+// raise (and the tile itself if the sweep cap stopped it).  With `check`, a
+// tile that has no raisable pixel is left alone.
+template <int CONN, bool kBounded>
+__device__ bool visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t, bool check, int npar,
+                           uint32_t* word, uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
   const TileRef tr = tile_ref(a, t);
   load_region<false>(tr, L);
-  if (check && !lds_dirty<CONN>(L, seeds)) return;
+  if (check && !lds_dirty<CONN>(L, seeds)) return false;
   const int l = lane();
   const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
@@ -469,88 +488,121 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t
   const bool changed = it > 1 || !stable;
   if (changed) store_tile(tr, L);
   const uint32_t m = changed ? border_marks<CONN>(L, ot, ob, ol, orr) : 0u;
-  // Candidate tiles in lanes 0..8 (8 = this tile when not yet stable).
-  int dy = 0, dx = 0;
-  bool want = false;
-  if (l < 8) {
-    // bit order of border_marks: top, bottom, left, right, tl, tr, bl, br
-    want = (m >> l) & 1u;
-    dy = l < 2 ? (l == 0 ? -1 : 1) : (l < 4 ? 0 : (l < 6 ? -1 : 1));
-    dx = l < 2 ? 0 : (l < 4 ? (l == 2 ? -1 : 1) : ((l & 1) ? 1 : -1));
-  } else if (l == 8) {
-    want = !stable;
-  }
-  const int ny = tr.ty + dy, nx = tr.tx + dx;
-  want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
-  mark_tiles(a, s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), npar, ncount);
+  return mark_reach<kBounded>(a, s, tr, m, !stable, npar, word);
 }
 
-// Rounds: round r visits the tiles of list r (parity r&1) and lists the tiles
-// to visit in round r+1.  A round whose list lost tiles to the capacity is
-// replaced by a full round that visits every tile holding a raisable pixel
-// (all flags cleared first), which restarts from the current image.
-template <int CONN>
+// Round 0 is the seed pass over every tile; round r >= 1 visits the tiles
+// flagged in round r-1 and flags the tiles of round r+1 (parity (r+1)&1,
+// word or count slot (r+1)%3).  Bounded mode: a round whose list lost tiles
+// to the capacity is replaced by a full round that visits every tile holding
+// a raisable pixel (all flags cleared first), restarting from the current
+// image.  The flags must be zero when the kernel starts.
+template <int CONN, bool kBounded>
 __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ uint32_t stage_mem[kWavesPerBlock][kBounded ? kStageCap : 1];
   __shared__ uint32_t decision[2];
-  const int w = threadIdx.x / kWave;
+  __shared__ uint32_t flagged;  // dense mode: this workgroup flagged a tile in this round
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
-  const uint32_t gw = blockIdx.x * kWavesPerBlock + w, nw = gridDim.x * kWavesPerBlock;
+  WaveStage s = {stage_mem[w], kBounded ? (uint32_t)kStageCap : 1u, 0u};
+  const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
+  if (threadIdx.x == 0) flagged = 0u;
   uint32_t gen = 0;
-  uint32_t visits = 0, iters = 0, rounds = 0, restarts = 0, seeds = 0;
-  for (uint32_t r = 0;; ++r) {
-    const int par = (int)(r & 1u), npar = 1 - par;
-    uint32_t* count = a.counts + (r % 3u) * 64u;
-    // Every workgroup reads the same words: nothing writes them between the
-    // previous barrier and this read (round r appends to list r+1).
-    if (threadIdx.x == 0) {
-      decision[0] = cload(count);
-      decision[1] = cload(a.lost + par * 64);
+  uint32_t visits = 0, iters = 0, seed_iters = 0, rounds = 0, restarts = 0, seeds = 0, first = 0;
+  bool ok = true, more = true;
+  {
+    uint32_t* word = a.counts + 64u;  // bounded mode: round 1 reads count slot 1
+    for (uint32_t t = gw; t < a.ntiles; t += nw)
+      if (seed_visit<CONN, kBounded>(a, L, s, t, word, seed_iters) && !kBounded && lane() == 0) flagged = 1u;
+    if (kBounded) {
+      tile_flush(s, a.lists + a.ntiles, word, a.list_cap, a.flags + a.ntiles, a.lost + 64);
+      ok = grid_barrier(a.bar, gen, a.stats);
+    } else {
+      ok = grid_barrier_or(a.bar, gen, a.stats, &flagged, more);
     }
-    __syncthreads();
-    uint32_t n = decision[0];
-    const bool full = decision[1] != 0u;
-    if (!full && n == 0u) break;
+  }
+  for (uint32_t r = 1; ok; ++r) {
+    const int par = (int)(r & 1u), npar = 1 - par;
+    uint32_t n = 0;
+    bool full = false;
+    if (kBounded) {
+      // Every workgroup reads the same words: nothing writes them between the
+      // previous barrier and this read (round r appends for round r+1).
+      if (threadIdx.x == 0) {
+        decision[0] = cload(a.counts + (r % 3u) * 64u);
+        decision[1] = cload(a.lost + par * 64);
+      }
+      __syncthreads();
+      n = decision[0];
+      full = decision[1] != 0u;
+      if (!full && n == 0u) break;
+    } else if (!more) {
+      break;
+    }
     if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
     }
-    if (full) {
-      if (!grid_barrier(a.bar, gen, a.stats)) break;  // everyone has read the decision
-      for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2u * a.ntiles; i += gridDim.x * blockDim.x)
-        cstore(a.flags + i, 0u);
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        cstore(a.lost, 0u);
-        cstore(a.lost + 64, 0u);
-        restarts++;
+    const uint32_t before = visits;
+    if (kBounded) {
+      if (full) {
+        if (!grid_barrier(a.bar, gen, a.stats)) break;  // everyone has read the decision
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2u * a.ntiles; i += gridDim.x * blockDim.x)
+          cstore(a.flags + i, 0u);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          cstore(a.lost, 0u);
+          cstore(a.lost + 64, 0u);
+          restarts++;
+        }
+        if (!grid_barrier(a.bar, gen, a.stats)) break;
       }
-      if (!grid_barrier(a.bar, gen, a.stats)) break;
-    }
-    // The count of round r+2 is reused: clear it now (it was last read in round
-    // r-1, and is next appended to in round r+1, after this round's barrier).
-    if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
-    uint32_t* ncount = a.counts + ((r + 1u) % 3u) * 64u;
-    if (full) {
-      for (uint32_t t = gw; t < a.ntiles; t += nw) visit_tile<CONN>(a, L, s, t, true, npar, ncount, visits, iters, seeds);
+      // The count of round r+2 is reused: clear it now (it was last read in
+      // round r-1, and is next appended to in round r+1, after this round's barrier).
+      if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
+      uint32_t* word = a.counts + ((r + 1u) % 3u) * 64u;
+      if (full) {
+        for (uint32_t t = gw; t < a.ntiles; t += nw)
+          visit_tile<CONN, kBounded>(a, L, s, t, true, npar, word, visits, iters, seeds);
+      } else {
+        if (n > a.list_cap) n = a.list_cap;
+        const uint32_t* list = a.lists + (size_t)par * a.ntiles;
+        for (uint32_t i = gw; i < n; i += nw) {
+          const uint32_t t = cload(list + i);
+          if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
+          visit_tile<CONN, kBounded>(a, L, s, t, false, npar, word, visits, iters, seeds);
+        }
+      }
+      tile_flush(s, a.lists + (size_t)npar * a.ntiles, word, a.list_cap, a.flags + (size_t)npar * a.ntiles,
+                 a.lost + npar * 64);
     } else {
-      if (n > a.list_cap) n = a.list_cap;
-      const uint32_t* list = a.lists + (size_t)par * a.ntiles;
-      for (uint32_t i = gw; i < n; i += nw) {
-        const uint32_t t = cload(list + i);
-        if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
-        visit_tile<CONN>(a, L, s, t, false, npar, ncount, visits, iters, seeds);
+      // This wave's share of the tiles: gw, gw + nw, gw + 2 nw, ...
+      uint32_t* flg = a.flags + (size_t)par * a.ntiles;
+      for (uint32_t base = gw; base < a.ntiles; base += nw * (uint32_t)kWave) {
+        const uint32_t mine = base + (uint32_t)lane() * nw;
+        uint64_t mm = ballot(mine < a.ntiles && cload(flg + mine) != 0u);
+        while (mm) {
+          const int b = __ffsll((long long)mm) - 1;
+          mm &= mm - 1;
+          const uint32_t t = base + (uint32_t)b * nw;
+          if (lane() == 0) cstore(flg + t, 0u);
+          if (visit_tile<CONN, kBounded>(a, L, s, t, false, npar, nullptr, visits, iters, seeds) && lane() == 0)
+            flagged = 1u;
+        }
       }
     }
-    tile_flush(s, a.lists + (size_t)npar * a.ntiles, ncount, a.list_cap, a.flags + (size_t)npar * a.ntiles,
-               a.lost + npar * 64);
+    if (r == 1) first = visits - before;
     rounds++;
-    if (!grid_barrier(a.bar, gen, a.stats)) break;
+    if (kBounded) {
+      if (!grid_barrier(a.bar, gen, a.stats)) break;
+    } else {
+      if (!grid_barrier_or(a.bar, gen, a.stats, &flagged, more)) break;
+    }
   }
   if (lane() == 0) {
+    stat_add(a.stats, kStatSeeds, (unsigned long long)first);
     stat_add(a.stats, kStatItems, visits);
-    stat_add(a.stats, kStatSweeps, iters);
+    stat_add(a.stats, kStatSweeps, iters + seed_iters);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     stat_add(a.stats, kStatRounds, rounds);
@@ -575,7 +627,6 @@ __global__ void k_tile_job(const MrJob* jobs, uint32_t njobs, uint32_t* tile_job
 // ---- host-side launch -----------------------------------------------------------------
 int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stream, Recorder* rec, const char** err) {
   using namespace mr;
-  const uint32_t seed_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (a.njobs > 1u) {
     const uint32_t b = (a.ntiles + 255u) / 256u;
     hipLaunchKernelGGL(k_tile_job, dim3(b < 1024u ? b : 1024u), dim3(256), 0, stream, a.jobs, a.njobs, a.tile_job, a.ntiles);
@@ -584,28 +635,13 @@ int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stre
       return -1;
     }
   }
-  rec->begin(1, stream);
-  if (conn == 8)
-    hipLaunchKernelGGL(k_seed<8>, dim3(seed_blocks), dim3(256), 0, stream, a);
-  else
-    hipLaunchKernelGGL(k_seed<4>, dim3(seed_blocks), dim3(256), 0, stream, a);
-  rec->end(stream);
-  if (hipGetLastError() != hipSuccess) {
-    *err = "seed-pass launch failed";
+  if (zero_words(a.flags, 2ull * a.ntiles, stream) != 0) {
+    *err = "flag reset launch failed";
     return -1;
   }
-  const uint32_t det_blocks = seed_blocks;
-  rec->begin(2, stream);
-  if (conn == 8)
-    hipLaunchKernelGGL(k_detect<8>, dim3(det_blocks), dim3(256), 0, stream, a);
-  else
-    hipLaunchKernelGGL(k_detect<4>, dim3(det_blocks), dim3(256), 0, stream, a);
-  rec->end(stream);
-  if (hipGetLastError() != hipSuccess) {
-    *err = "seed-detect launch failed";
-    return -1;
-  }
-  void* fn = conn == 8 ? reinterpret_cast<void*>(&k_propagate<8>) : reinterpret_cast<void*>(&k_propagate<4>);
+  const bool bounded = a.list_cap < a.ntiles;
+  void* fn = conn == 8 ? (bounded ? reinterpret_cast<void*>(&k_propagate<8, true>) : reinterpret_cast<void*>(&k_propagate<8, false>))
+                       : (bounded ? reinterpret_cast<void*>(&k_propagate<4, true>) : reinterpret_cast<void*>(&k_propagate<4, false>));
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) {

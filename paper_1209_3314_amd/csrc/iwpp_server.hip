@@ -7,10 +7,11 @@
 // batches, which fills it with many small tiles at once.
 //
 // Concurrency: one worker thread owns the device side (streams, arena,
-// batches); submit/poll/drain/stats take a mutex shared with it.  At most two
-// batches are queued on the compute stream, so the device goes from one batch
-// to the next without a host round trip while later arrivals still join the
-// batch after.  Batches share the context's fixed area and one scratch buffer:
+// batches); submit/poll/drain/stats take a mutex shared with it.  A batch
+// takes the admitted jobs whose uploads have finished; at most two batches are
+// queued on the compute stream, so the device goes from one batch to the next
+// without a host round trip while later arrivals still join the batch after,
+// and uploads, computation and downloads of successive batches overlap.  Batches share the context's fixed area and one scratch buffer:
 // they run one after another in stream order.
 #include <hip/hip_runtime.h>
 #include <time.h>
@@ -102,18 +103,19 @@ struct SJob {
   int64_t done_ns = 0;
   int32_t state = IWPP_JOB_QUEUED;
   size_t off = 0, bytes = 0;
-  iwpp_job dev{};  // the same job on device buffers
+  iwpp_job dev{};             // the same job on device buffers
+  hipEvent_t up = nullptr;    // recorded after the job's uploads
 };
 
 struct Batch {
   std::vector<uint64_t> tickets;
-  hipEvent_t up = nullptr, done = nullptr, down = nullptr;
+  hipEvent_t done = nullptr, down = nullptr;
   int slot = -1;
   size_t scratch = 0;
 };
 
-constexpr int kSlots = 3;           // pinned table/statistics slots (≤ 2 batches in flight + 1)
-constexpr int kMaxQueuedBatches = 2;
+constexpr int kSlots = 4;             // pinned table/statistics slots = batches in flight at most
+constexpr int kMaxComputingBatches = 2;  // batches queued or running on the compute stream
 constexpr size_t kStatWords = iwpp::kStatShards * iwpp::kStatFields;
 
 }  // namespace
@@ -200,6 +202,8 @@ struct iwpp_server {
           SJob& j = jobs[t];
           j.state = ok ? IWPP_JOB_DONE : IWPP_JOB_FAILED;
           j.done_ns = now;
+          put_event(j.up);
+          j.up = nullptr;
           arena.release(j.off, j.bytes);
           if (ok)
             st.completed++;
@@ -209,7 +213,6 @@ struct iwpp_server {
         }
       }
       slot_busy[b.slot] = false;
-      put_event(b.up);
       put_event(b.done);
       put_event(b.down);
       inflight.pop_front();
@@ -263,8 +266,11 @@ struct iwpp_server {
         d.out1 = base + align256(np) + align256(4 * np);
         ok = hipMemcpyAsync(base, j->host.in0, np, hipMemcpyHostToDevice, h2d) == hipSuccess;
       }
+      hipEvent_t up = ok ? get_event() : nullptr;
+      ok = ok && up && hipEventRecord(up, h2d) == hipSuccess;
       if (!ok) {
         (void)hipGetLastError();
+        put_event(up);
         arena.release(off, bytes);
         broken = true;
         set_error("serving: upload failed");
@@ -276,6 +282,7 @@ struct iwpp_server {
         j->off = off;
         j->bytes = bytes;
         j->dev = d;
+        j->up = up;
         j->state = IWPP_JOB_ADMITTED;
         st.queued_now--;
         st.admitted_now++;
@@ -290,7 +297,11 @@ struct iwpp_server {
 
   // Launch the admitted jobs as one batch when the compute stream has room.
   bool launch() {
-    if (admitted.empty() || (int)inflight.size() >= kMaxQueuedBatches || broken) return false;
+    if (admitted.empty() || broken) return false;
+    int computing = 0;
+    for (const Batch& q : inflight)
+      if (hipEventQuery(q.done) == hipErrorNotReady) computing++;
+    if (computing >= kMaxComputingBatches) return false;
     int slot = -1;
     for (int s = 0; s < kSlots; ++s)
       if (!slot_busy[s]) {
@@ -298,16 +309,28 @@ struct iwpp_server {
         break;
       }
     if (slot < 0) return false;
+    // The batch takes the admitted jobs, in order, whose uploads have
+    // finished: while it computes, later uploads and the previous batch's
+    // downloads proceed on the copy streams.
     std::vector<iwpp_job> dj;
     std::vector<uint64_t> tk;
     {
       std::lock_guard<std::mutex> g(mu);
       for (uint64_t t : admitted) {
         if ((int)dj.size() >= opt.max_batch) break;
+        const hipError_t q = hipEventQuery(jobs[t].up);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          (void)hipGetLastError();
+          broken = true;
+          error = error.empty() ? "serving: upload failed on the device" : error;
+          return false;
+        }
         dj.push_back(jobs[t].dev);
         tk.push_back(t);
       }
     }
+    if (dj.empty()) return false;
     iwpp::rt::Plan plan;
     size_t n = dj.size();
     for (;;) {  // shrink the batch until its scratch and tables fit
@@ -329,15 +352,13 @@ struct iwpp_server {
     Batch b;
     b.tickets = tk;
     b.slot = slot;
-    b.up = get_event();
     b.done = get_event();
     b.down = get_event();
     const size_t sb = align256(plan.scratch_bytes);
     uint8_t* tables = scratch + sb;
     iwpp::rt::pack_tables(plan, slot_tables(slot));
     iwpp::Recorder off;
-    bool ok = b.up && b.done && b.down && hipEventRecord(b.up, h2d) == hipSuccess &&
-              hipStreamWaitEvent(comp, b.up, 0) == hipSuccess;
+    bool ok = b.done && b.down;
     if (ok && plan.table_bytes)
       ok = hipMemcpyAsync(tables, slot_tables(slot), plan.table_bytes, hipMemcpyHostToDevice, comp) == hipSuccess;
     bool first = true;
@@ -396,6 +417,8 @@ struct iwpp_server {
           admitted.pop_front();
           j.state = IWPP_JOB_FAILED;
           j.done_ns = mono_ns();
+          put_event(j.up);
+          j.up = nullptr;
           arena.release(j.off, j.bytes);
           st.failed++;
           st.admitted_now--;

@@ -177,3 +177,36 @@ def serve_trace(rate: float, duration_s: float, seed: int = 0, sigma: float = 0.
         out.append((t, spec))
         k += 1
     return out
+
+
+def serve_pool(size: int = 64, seed: int = 0, sigma: float = 0.7) -> list:
+    """A bounded pool of request inputs drawn like ``serve_trace``'s requests
+    (square sides round(1024 * exp(sigma * Z)) clipped to [256, 8192]); exactly
+    round(0.7 * size) reconstruction tiles, the rest EDT.  Generating one input
+    per request is too slow for long traces, so requests reuse pool items."""
+    rng = np.random.default_rng([13, seed])
+    n_mr = int(round(0.7 * size))
+    out = []
+    for k in range(size):
+        side = int(np.clip(round(1024.0 * math.exp(sigma * float(rng.standard_normal()))), 256, 8192))
+        s = 200000 + seed * 1000003 + k
+        if k < n_mr:
+            out.append({"op": "mr", "h": side, "w": side, "seed": s, "conn": 8,
+                        "n_disks": int(round(MR_DISK_DENSITY * side * side)), "offset": int(rng.integers(16, 65))})
+        else:
+            out.append({"op": "edt", "h": side, "w": side, "seed": s, "conn": 8,
+                        "coverage": float(rng.uniform(0.10, 0.50))})
+    return out
+
+
+def serve_arrivals(rate: float, duration_s: float, pool_size: int, seed: int = 0) -> list:
+    """Open-loop Poisson arrivals at ``rate`` per second over ``duration_s``,
+    each naming a pool item uniformly at random: a list of (time_s, index)."""
+    rng = np.random.default_rng([17, seed, int(rate)])
+    out = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration_s:
+            return out
+        out.append((t, int(rng.integers(pool_size))))

@@ -37,3 +37,14 @@ def test_serve_trace():
     times = [t for t, _ in tr]
     assert times == sorted(times)
     assert all(256 <= s["h"] <= 8192 for _, s in tr)
+
+
+def test_serve_pool_and_arrivals():
+    pool = synth.serve_pool(40, seed=1)
+    assert sum(p["op"] == "mr" for p in pool) == 28
+    assert all(256 <= p["h"] == p["w"] <= 8192 for p in pool)
+    arr = synth.serve_arrivals(500.0, 2.0, 40, seed=1)
+    assert 800 < len(arr) < 1200
+    assert [t for t, _ in arr] == sorted(t for t, _ in arr)
+    assert all(0 <= i < 40 for _, i in arr)
+    assert arr == synth.serve_arrivals(500.0, 2.0, 40, seed=1)
