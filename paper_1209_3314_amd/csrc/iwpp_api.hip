@@ -109,7 +109,8 @@ size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
   const uint64_t t = (uint64_t)((h + ts - 1) / ts) * (uint64_t)((w + ts - 1) / ts);
   const uint64_t np = (uint64_t)h * (uint64_t)w;
   // 5 tile words (+ alignment slack of the per-group arrays is added by the caller)
-  return (size_t)(20 * t + (op == IWPP_OP_EDT ? 8 * np : 0) + (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
+  return (size_t)(20 * t + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad : 0) +
+                  (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -277,7 +278,7 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     lr = iwpp::mr_launch(a, g.conn, ctx->opt.persistent_blocks, st, rec, &e);
   } else {
     iwpp::EdtArgs a{};
-    const size_t fb = align256(g.npix * 4);
+    const size_t fb = align256(g.npix * 4) + iwpp::kEdtStatePad;
     a.job0 = g.edt[0];
     a.njobs = nj;
     a.npix = g.npix;

@@ -76,49 +76,61 @@ __device__ __forceinline__ TileRef tile_ref(const EdtArgs& a, uint32_t t) {
   return r;
 }
 
-// Buffer resource over the image rows [row0, row0 + rows) of a per-pixel u32 array.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const uint32_t* base, const EdtJob& j, int row0, int rows) {
-  return make_rsrc(base + j.pix_base + (unsigned long long)row0 * (uint32_t)j.w, (uint32_t)rows * (uint32_t)j.w * 4u);
+// Buffer resource over the image rows [row0, row0 + rows) of a per-pixel u32
+// array, plus `pad` bytes after them (the state buffers are padded so that a
+// 16-byte load cut by the end of the last row stays inside).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const uint32_t* base, const EdtJob& j, int row0, int rows,
+                                                            uint32_t pad = 0u) {
+  return make_rsrc(base + j.pix_base + (unsigned long long)row0 * (uint32_t)j.w, (uint32_t)rows * (uint32_t)j.w * 4u + pad);
 }
 
+// Region in LDS: 34 rows; row pitch 40 words, tile column x at word 4 + x
+// (the halo at words 3 and 36), so that a row is ten aligned 16-byte chunks
+// starting at tile column -4.
+constexpr int PE = 40;
+constexpr int kC0 = 4;
 struct WaveLds {
-  uint32_t F[RP * RP];
+  uint32_t F[RP * PE];
 };
 
+// Offset that makes a raw buffer access fall outside every buffer (reads 0).
+constexpr uint32_t kOutside = 0xFFFFFFF0u;
+constexpr uint32_t kStatePad = 16u;  // readable bytes after the last pixel of a state buffer
+static_assert(kStatePad <= kEdtStatePad, "state buffers must be padded");
+
 // Load the tile of `src` and its halo into LDS (kNone outside the image).
+// 34 rows x 10 chunks of four words, six per lane, all as 16-byte loads with
+// no branches between them, so the wave waits for memory once per visit.
+// Chunks reaching outside the image are loaded anyway (or pointed outside the
+// buffer) and their outside words replaced by kNone.
 __device__ void load_region(const uint32_t* src, const TileRef& tr, WaveLds& L) {
   const EdtJob& j = tr.j;
   const int y0 = tr.ty * TE, x0 = tr.tx * TE;
   const int row0 = y0 > 0 ? y0 - 1 : 0;
   const int row1 = y0 + TE + 1 < j.h ? y0 + TE + 1 : j.h;
-  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(src, j, row0, row1 - row0);
-  // 34 rows x 10 items: eight 16-byte chunks of the tile row, two halo words.
-  for (int idx = lane(); idx < RP * 10; idx += kWave) {
-    const int ry = idx / 10, item = idx - ry * 10;
-    const int y = y0 - 1 + ry;
+  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(src, j, row0, row1 - row0, kStatePad);
+  constexpr int kChunks = RP * 10;
+  constexpr int kPer = (kChunks + kWave - 1) / kWave;
+  v4u v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int idx = lane() + k * kWave;
+    const int ry = idx / 10, c = idx - ry * 10;
+    const int y = y0 - 1 + ry, xs = x0 - kC0 + 4 * c;
+    const bool ok = idx < kChunks && y >= 0 && y < j.h && xs >= 0 && xs < j.w;
+    const uint32_t off = ok ? ((uint32_t)(y - row0) * (uint32_t)j.w + (uint32_t)xs) * 4u : kOutside;
+    v[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kSc1));
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int idx = lane() + k * kWave;
+    const int ry = idx / 10, c = idx - ry * 10;
+    const int y = y0 - 1 + ry, xs = x0 - kC0 + 4 * c;
     const bool row_ok = y >= 0 && y < j.h;
-    const uint32_t rowoff = (uint32_t)(row_ok ? y - row0 : 0) * (uint32_t)j.w;
-    uint32_t* dst = &L.F[ry * RP];
-    if (item < 8) {
-      const int xs = x0 + item * 4;
-      v4u v = {kNone, kNone, kNone, kNone};
-      if (row_ok && xs < j.w) {
-        if (xs + 4 <= j.w) {
-          v = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, (rowoff + (uint32_t)xs) * 4u, 0, kSc1));
-        } else {
+    v4u o;
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (xs + b < j.w) v[b] = __builtin_amdgcn_raw_buffer_load_b32(rs, (rowoff + (uint32_t)(xs + b)) * 4u, 0, kSc1);
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) dst[1 + item * 4 + b] = v[b];
-    } else {
-      const int x = item == 8 ? x0 - 1 : x0 + TE;
-      uint32_t v = kNone;
-      if (row_ok && x >= 0 && x < j.w) v = __builtin_amdgcn_raw_buffer_load_b32(rs, (rowoff + (uint32_t)x) * 4u, 0, kSc1);
-      dst[item == 8 ? 0 : RP - 1] = v;
-    }
+    for (int b = 0; b < 4; ++b) o[b] = (row_ok && xs + b >= 0 && xs + b < j.w) ? v[k][b] : kNone;
+    if (idx < kChunks) *reinterpret_cast<v4u*>(&L.F[ry * PE + 4 * c]) = o;
   }
   wave_sync();
 }
@@ -144,18 +156,18 @@ __device__ uint32_t relax_tile(const WaveLds& L, uint32_t* dst, const TileRef& t
     const int y = yb + 2 * k;
     const int qy = y0 + y;
     const uint32_t q = pack_yx(qy, qx);
-    const uint32_t* c = &L.F[(y + 1) * RP + x + 1];
+    const uint32_t* c = &L.F[(y + 1) * PE + kC0 + x];
     const uint32_t old = c[0];
     unsigned long long best = ((unsigned long long)d2(q, old) << 32) | old;
-    offer(q, c[-RP], best);
-    offer(q, c[RP], best);
+    offer(q, c[-PE], best);
+    offer(q, c[PE], best);
     offer(q, c[-1], best);
     offer(q, c[1], best);
     if (CONN == 8) {
-      offer(q, c[-RP - 1], best);
-      offer(q, c[-RP + 1], best);
-      offer(q, c[RP - 1], best);
-      offer(q, c[RP + 1], best);
+      offer(q, c[-PE - 1], best);
+      offer(q, c[-PE + 1], best);
+      offer(q, c[PE - 1], best);
+      offer(q, c[PE + 1], best);
     }
     const uint32_t bf = (uint32_t)best;
     const bool inside = qy < j.h && qx < j.w;

@@ -11,6 +11,7 @@ struct GridBarrier;
 // Tile geometry shared by the host plans and the kernels.
 constexpr int kMrTile = 64;   // reconstruction tiles: 64 x 64 pixels
 constexpr int kEdtTile = 32;  // EDT tiles: 32 x 32 pixels
+constexpr size_t kEdtStatePad = 256;  // bytes after each EDT state buffer (16-byte loads may cross the end)
 
 // One reconstruction image of a launch.
 struct MrJob {

@@ -91,10 +91,21 @@ __device__ __forceinline__ TileRef tile_ref(const MrArgs& a, uint32_t t) {
   return r;
 }
 
+// Offset that makes a raw buffer access fall outside every buffer (reads 0).
+constexpr uint32_t kOutside = 0xFFFFFFF0u;
+
 // Load the (T+2) x (T+2) region of tile (ty, tx) -- the tile and its one-pixel
 // halo -- into LDS.  Pixels outside the image read as J = I = 0, which can
 // neither raise nor be raised, i.e. they are not neighbours.  In the seed pass
-// J is the marker clamped to the mask.
+// J is the marker clamped to the mask.  The 66 rows are 264 chunks of 16
+// bytes (five per lane) plus 132 halo bytes, each read as the 4-byte word
+// that ends at it (three per lane); every load is issued, with no branch in
+// between, before the first LDS write, so a visit waits for memory once.
+// Loads that would leave the image are pointed outside the buffer (they read
+// 0; a raw buffer load that crosses the buffer's end reads 0 as a whole, so
+// no load may reach past the image).  A chunk cut by the right edge of the
+// image -- one chunk column of the tiles at that edge -- is read byte by byte
+// in a second pass.
 template <bool kSeed>
 __device__ void load_region(const TileRef& tr, WaveLds& L) {
   const MrJob& a = tr.j;
@@ -102,52 +113,78 @@ __device__ void load_region(const TileRef& tr, WaveLds& L) {
   const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
   const __amdgpu_buffer_rsrc_t rj = make_rsrc(kSeed ? a.marker : a.out, total);
   const __amdgpu_buffer_rsrc_t ri = make_rsrc(a.mask, total);
-  // 66 rows x 5 items: four 16-byte chunks of the tile row, and the two halo columns.
-  for (int idx = lane(); idx < kRows * 5; idx += kWave) {
-    const int ry = idx / 5, item = idx - ry * 5;
-    const int y = y0 - 1 + ry;
-    const bool row_ok = y >= 0 && y < a.h;
-    const uint32_t rowoff = (uint32_t)(row_ok ? y : 0) * (uint32_t)a.w;
-    if (item < 4) {
-      const int xs = x0 + item * 16;
-      v4u vj = {0u, 0u, 0u, 0u}, vi = {0u, 0u, 0u, 0u};
-      if (row_ok && xs < a.w) {
-        const uint32_t off = rowoff + (uint32_t)xs;
-        if (xs + 16 <= a.w) {
-          vj = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rj, off, 0, kSc1));
-          vi = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ri, off, 0, kSc1));
-        } else {
-          const int nb = a.w - xs;
+  const int rem = a.w - x0;  // image columns from this tile's first column on
+  const int cp = (rem < T && (rem & 15) != 0) ? rem >> 4 : -1;  // the cut chunk column, if any
+  constexpr int kMain = kRows * 4, kHalo = kRows * 2;
+  constexpr int kPerMain = (kMain + kWave - 1) / kWave, kPerHalo = (kHalo + kWave - 1) / kWave;
+  v4u vj[kPerMain], vi[kPerMain];
+  uint32_t hj[kPerHalo], hi[kPerHalo];
 #pragma unroll
-          for (int b = 0; b < 16; ++b) {
-            if (b < nb) {
-              vj[b >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rj, off + b, 0, kSc1) << (8 * (b & 3));
-              vi[b >> 2] |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(ri, off + b, 0, kSc1) << (8 * (b & 3));
-            }
-          }
+  for (int k = 0; k < kPerMain; ++k) {
+    const int idx = lane() + k * kWave;
+    const int c = idx & 3;
+    const int y = y0 - 1 + (idx >> 2), xs = x0 + 16 * c;
+    const bool ok = idx < kMain && y >= 0 && y < a.h && xs + 16 <= a.w;
+    const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)xs : kOutside;
+    vj[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rj, off, 0, kSc1));
+    vi[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ri, off, 0, kSc1));
+  }
+#pragma unroll
+  for (int k = 0; k < kPerHalo; ++k) {
+    const int idx = lane() + k * kWave;
+    const int y = y0 - 1 + (idx >> 1);
+    const int x = (idx & 1) ? x0 + T : x0 - 1;
+    const bool ok = idx < kHalo && y >= 0 && y < a.h && x >= 3 && x < a.w;
+    const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)(x - 3) : kOutside;
+    hj[k] = __builtin_amdgcn_raw_buffer_load_b32(rj, off, 0, kSc1);
+    hi[k] = __builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, kSc1);
+  }
+#pragma unroll
+  for (int k = 0; k < kPerMain; ++k) {
+    const int idx = lane() + k * kWave;
+    if (idx >= kMain) continue;
+    const int ry = idx >> 2, c = idx & 3;
+    uint32_t* dj = reinterpret_cast<uint32_t*>(&L.J[lidx(ry - 1, c * 16)]);
+    uint32_t* di = reinterpret_cast<uint32_t*>(&L.I[lidx(ry - 1, c * 16)]);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      dj[d] = kSeed ? min_u8x4(vj[k][d], vi[k][d]) : vj[k][d];
+      di[d] = vi[k][d];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPerHalo; ++k) {
+    const int idx = lane() + k * kWave;
+    if (idx >= kHalo) continue;
+    const int ry = idx >> 1;
+    const uint32_t jb = hj[k] >> 24, ib = hi[k] >> 24;
+    const int at = lidx(ry - 1, (idx & 1) ? T : -1);
+    L.J[at] = (uint8_t)(kSeed ? umin(jb, ib) : jb);
+    L.I[at] = (uint8_t)ib;
+  }
+  if (cp >= 0) {  // wave-uniform: only tiles cut by the right edge of the image
+    const int nb = rem - 16 * cp, xs = x0 + 16 * cp;
+#pragma unroll
+    for (int k = 0; k < (kRows + kWave - 1) / kWave; ++k) {
+      const int ry = lane() + k * kWave;
+      const int y = y0 - 1 + ry;
+      const bool row_ok = ry < kRows && y >= 0 && y < a.h;
+      uint32_t bj[15], bi[15];
+#pragma unroll
+      for (int b = 0; b < 15; ++b) {
+        const uint32_t off = (row_ok && b < nb) ? (uint32_t)y * (uint32_t)a.w + (uint32_t)(xs + b) : kOutside;
+        bj[b] = __builtin_amdgcn_raw_buffer_load_b8(rj, off, 0, kSc1);
+        bi[b] = __builtin_amdgcn_raw_buffer_load_b8(ri, off, 0, kSc1);
+      }
+      if (ry < kRows) {
+#pragma unroll
+        for (int b = 0; b < 15; ++b) {
+          if (b >= nb) break;
+          const int at = lidx(ry - 1, 16 * cp + b);
+          L.J[at] = (uint8_t)(kSeed ? umin(bj[b], bi[b]) : bj[b]);
+          L.I[at] = (uint8_t)bi[b];
         }
       }
-      uint32_t* dj = reinterpret_cast<uint32_t*>(&L.J[lidx(ry - 1, item * 16)]);
-      uint32_t* di = reinterpret_cast<uint32_t*>(&L.I[lidx(ry - 1, item * 16)]);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        dj[k] = kSeed ? min_u8x4(vj[k], vi[k]) : vj[k];
-        di[k] = vi[k];
-      }
-    } else {
-      uint32_t jl = 0, il = 0, jr = 0, ir = 0;
-      if (row_ok && x0 > 0) {
-        jl = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + (uint32_t)(x0 - 1), 0, kSc1);
-        il = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + (uint32_t)(x0 - 1), 0, kSc1);
-      }
-      if (row_ok && x0 + T < a.w) {
-        jr = __builtin_amdgcn_raw_buffer_load_b8(rj, rowoff + (uint32_t)(x0 + T), 0, kSc1);
-        ir = __builtin_amdgcn_raw_buffer_load_b8(ri, rowoff + (uint32_t)(x0 + T), 0, kSc1);
-      }
-      L.J[lidx(ry - 1, -1)] = (uint8_t)(kSeed ? umin(jl, il) : jl);
-      L.I[lidx(ry - 1, -1)] = (uint8_t)il;
-      L.J[lidx(ry - 1, T)] = (uint8_t)(kSeed ? umin(jr, ir) : jr);
-      L.I[lidx(ry - 1, T)] = (uint8_t)ir;
     }
   }
   wave_sync();

@@ -42,7 +42,7 @@ struct Group {
   // EDT: feat0 | feat1 | flags[2][T] | lists[2][T] | tile_job[T].
   size_t scratch_bytes() const {
     const size_t tb = align256(ntiles * 4);
-    return (op == IWPP_OP_EDT ? 2 * align256(npix * 4) : 0) + 5 * tb;
+    return (op == IWPP_OP_EDT ? 2 * (align256(npix * 4) + iwpp::kEdtStatePad) : 0) + 5 * tb;
   }
 };
 
