@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--serve-burst", type=int, default=256, help="requests of the capacity burst (0 = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for rocprofv3 byte counters)")
+    ap.add_argument("--copy-first", action="store_true",
+                    help="run the 1 GiB reference copy 3 times before the workload (same process, for counter runs)")
     args = ap.parse_args()
     if args.calibrate_copy:
         import torch
@@ -362,6 +364,14 @@ def main():
     from paper_1209_3314_amd import synth
 
     dev = torch.device("cuda", 0)
+    if args.copy_first:
+        ca = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        cb = torch.empty_like(ca)
+        for _ in range(3):
+            cb.copy_(ca)
+        torch.cuda.synchronize()
+        del ca, cb
+        log("reference copy: 3 x 1 GiB device-to-device")
     t = time.time()
     Jm, Im = synth.workload_mr_16k()
     Be = synth.workload_edt_4k()
