@@ -109,7 +109,7 @@ size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
   const uint64_t t = (uint64_t)((h + ts - 1) / ts) * (uint64_t)((w + ts - 1) / ts);
   const uint64_t np = (uint64_t)h * (uint64_t)w;
   // 5 tile words (+ alignment slack of the per-group arrays is added by the caller)
-  return (size_t)(20 * t + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad : 0) +
+  return (size_t)(80 * t + 20 * 256 + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad : 0) +
                   (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
 }
 
@@ -269,7 +269,8 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.seed_sweeps = ctx->opt.mr_seed_sweeps > 0 ? ctx->opt.mr_seed_sweeps : 64;
     a.flags = reinterpret_cast<uint32_t*>(scratch);
     a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * tb);
-    a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 4 * tb) : nullptr;
+    a.unsettled = reinterpret_cast<uint32_t*>(scratch + 18 * tb);
+    a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 19 * tb) : nullptr;
     a.jobs = nj > 1 ? reinterpret_cast<const iwpp::MrJob*>(tables + g.table_off) : nullptr;
     a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
     a.lost = reinterpret_cast<uint32_t*>(fixed + kOffLost);
@@ -287,7 +288,7 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.feat1 = reinterpret_cast<uint32_t*>(scratch + fb);
     a.flags = reinterpret_cast<uint32_t*>(scratch + 2 * fb);
     a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * fb + 2 * tb);
-    a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 2 * fb + 4 * tb) : nullptr;
+    a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 2 * fb + 18 * tb) : nullptr;
     a.jobs = nj > 1 ? reinterpret_cast<const iwpp::EdtJob*>(tables + g.table_off) : nullptr;
     a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
     a.ovf = reinterpret_cast<uint32_t*>(fixed + kOffOvf);

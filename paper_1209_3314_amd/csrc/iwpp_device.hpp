@@ -218,4 +218,77 @@ __device__ __forceinline__ void stage_append(WaveStageT<Item>& s, bool pred, Ite
   s.n += k;
 }
 
+// ---- sharded tile frontier --------------------------------------------------------
+// A round's work list of tiles is split into kShards sub-lists, one per group of
+// workgroups (blockIdx & 7, i.e. one per XCD).  A wave stages its appends in LDS
+// and flushes them into its group's sub-list with one atomic on that sub-list's
+// counter, so each counter sees an eighth of the flushes.  Consumers read the
+// kShards counters and split the concatenation evenly over all waves, so a
+// round's work is balanced whatever the tiles' positions.  A per-tile flag word
+// (set with atomic_or) keeps a tile on a round's list at most once.
+constexpr int kShards = 8;
+
+// Counter of (round slot, shard): 256 bytes apart.
+__device__ __forceinline__ uint32_t* shard_count(uint32_t* counts, uint32_t slot, uint32_t shard) {
+  return counts + (slot * (uint32_t)kShards + shard) * 64u;
+}
+
+// Flush the stage into sub-list `list` (capacity `cap`) counted by `count`.
+// Items past the capacity are dropped: their flag is cleared (so a later mark
+// can list them again) and *lost is set.
+__device__ inline void shard_flush(WaveStage& s, uint32_t* list, uint32_t* count, uint32_t cap, uint32_t* flags,
+                                   uint32_t* lost) {
+  const uint32_t n = s.n;
+  if (n == 0) return;
+  wave_sync();
+  uint32_t base = 0;
+  if (lane() == 0) base = atomic_add(count, n);
+  base = readlane(base, 0);
+  bool dropped = false;
+  for (uint32_t i = lane(); i < n; i += kWave) {
+    const uint32_t slot = base + i, item = s.items[i];
+    if (slot < cap) {
+      cstore(list + slot, item);
+    } else {
+      cstore(flags + item, 0u);
+      dropped = true;
+    }
+  }
+  if (ballot(dropped) && lane() == 0) cstore(lost, 1u);
+  wave_sync();
+  s.n = 0;
+}
+
+// Stage tile t (every lane with `pred`) unless it is already on the list
+// whose flags are `flags`; flushes first if the stage could overflow.
+__device__ inline void shard_mark(WaveStage& s, bool pred, uint32_t t, uint32_t* flags, uint32_t* list,
+                                  uint32_t* count, uint32_t cap, uint32_t* lost) {
+  const bool fresh = pred && atomic_or(flags + t, 1u) == 0u;
+  const uint64_t m = ballot(fresh);
+  if (m == 0) return;
+  const uint32_t k = (uint32_t)__popcll(m);
+  if (s.n + k > s.cap) shard_flush(s, list, count, cap, flags, lost);
+  if (fresh) s.items[s.n + mbcnt(m)] = t;
+  s.n += k;
+}
+
+// Length of round slot `slot`'s list: per-shard counts (capped) into `cnt`
+// (kShards entries in LDS, filled by threads 0..kShards-1 of the workgroup).
+__device__ __forceinline__ void shard_counts(uint32_t* counts, uint32_t slot, uint32_t cap, uint32_t* cnt) {
+  if (threadIdx.x < (unsigned)kShards) {
+    const uint32_t c = cload(shard_count(counts, slot, threadIdx.x));
+    cnt[threadIdx.x] = c < cap ? c : cap;
+  }
+}
+
+// Item i of the concatenated sub-lists of one parity (lists: [kShards][stride]).
+__device__ __forceinline__ uint32_t shard_item(const uint32_t* lists, uint32_t stride, const uint32_t* cnt, uint32_t i) {
+  uint32_t x = 0;
+  while (x + 1 < (uint32_t)kShards && i >= cnt[x]) {
+    i -= cnt[x];
+    ++x;
+  }
+  return cload(lists + (size_t)x * stride + i);
+}
+
 }  // namespace iwpp

@@ -21,10 +21,11 @@
 // pixels.  A tile that is not visited in a round keeps equal values in both
 // buffers: a tile changes only in rounds it is visited, and after a round in
 // which it changed it is visited again, so it stops being visited only after a
-// round in which it (re)wrote its unchanged values.  The frontier of tiles is
-// a dense array of per-tile flags, set by plain stores and cleared by the wave
-// that visits the tile; every wave scans its own share of it each round, so
-// building the frontier needs no counter and no atomic.
+// round in which it (re)wrote its unchanged values.  The tiles of a round are
+// a work list split into eight sub-lists, one per group of workgroups (one
+// per XCD), appended to with one atomic per wave flush and consumed evenly by
+// all waves in the next round; a per-tile flag keeps a tile on a round's list
+// once.
 //
 // State is the feature's packed coordinates (y << 16 | x), 4 bytes per pixel.
 // A candidate's squared distance is one saturating packed 16-bit subtraction
@@ -41,6 +42,7 @@ namespace edt {
 constexpr int TE = kEdtTile;      // tile side
 constexpr int RP = TE + 2;        // region side with the halo
 constexpr int kWavesPerBlock = 4;
+constexpr int kStageCap = 128;
 constexpr uint32_t kNone = 0x80008000u;
 constexpr uint32_t kMaxRounds = 1u << 20;
 
@@ -194,12 +196,29 @@ __device__ uint32_t relax_tile(const WaveLds& L, uint32_t* dst, const TileRef& t
   return m;
 }
 
-// Flag, for the round of parity `par`, the tiles that the changes of tile tr
-// (mask m of relax_tile, or of the initial state) reach: itself (bit 0) and
-// each neighbour whose halo holds a changed pixel.  Lanes 0..8 of the wave
-// each handle one candidate.  Returns (wave-uniform) whether any tile was
-// flagged.
-__device__ __forceinline__ bool flag_reach(const EdtArgs& a, const TileRef& tr, uint32_t m, int par) {
+// The list of round r+1 while round r runs (r = 0 for the initial frontier):
+// the parity's flags and the sub-list of this workgroup's group.
+struct Next {
+  uint32_t* flags;
+  uint32_t* list;
+  uint32_t* count;
+};
+
+__device__ __forceinline__ Next next_frontier(const EdtArgs& a, uint32_t r) {
+  const uint32_t par = (r + 1u) & 1u, shard = blockIdx.x & (uint32_t)(kShards - 1);
+  Next n;
+  n.flags = a.flags + (size_t)par * a.ntiles;
+  n.list = a.lists + ((size_t)par * kShards + shard) * a.ntiles;
+  n.count = shard_count(a.counts, (r + 1u) % 3u, shard);
+  return n;
+}
+
+// List, for the next round, the tiles that the changes of tile tr (mask m of
+// relax_tile, or of the initial state) reach: itself (bit 0) and each
+// neighbour whose halo holds a changed pixel.  Lanes 0..8 of the wave each
+// handle one candidate.
+__device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const Next& nx, const TileRef& tr,
+                                           uint32_t m) {
   const int l = lane();
   int dy = 0, dx = 0;
   bool want = false;
@@ -212,22 +231,23 @@ __device__ __forceinline__ bool flag_reach(const EdtArgs& a, const TileRef& tr, 
     dy = k == 0 ? -1 : (k == 1 ? 1 : (k < 4 ? 0 : (k < 6 ? -1 : 1)));
     dx = k < 2 ? 0 : (k == 2 ? -1 : (k == 3 ? 1 : ((k & 1) ? 1 : -1)));
   }
-  const int ny = tr.ty + dy, nx = tr.tx + dx;
-  want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
-  if (want) cstore(a.flags + (size_t)par * a.ntiles + tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), 1u);
-  return ballot(want) != 0u;
+  const int ny = tr.ty + dy, nx_ = tr.tx + dx;
+  want = want && ny >= 0 && ny < tr.j.tiles_y && nx_ >= 0 && nx_ < tr.j.tiles_x;
+  shard_mark(s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx_), nx.flags, nx.list, nx.count, a.ntiles,
+             a.ovf);
 }
 
 // Initial state (features carry themselves, everything else none) in both
 // buffers, the contour-feature count (Algorithm 6's initial queue), and the
-// first round's flags: the tiles holding a non-feature pixel next to a
+// first round's list: the tiles holding a non-feature pixel next to a
 // feature (exactly the pixels round 1 changes) and the neighbours whose halo
 // holds one.  One wave per tile; the binary region is staged in LDS.  The
-// flags must be zero beforehand.
+// flags and counts must be zero beforehand.
 template <int CONN>
 __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   constexpr int BP = RP + 2;  // byte pitch
   __shared__ uint8_t binl[kWavesPerBlock][RP * BP];
+  __shared__ uint32_t stage_mem[kWavesPerBlock][16];
   const int w = threadIdx.x / kWave;
   const uint32_t t = blockIdx.x * kWavesPerBlock + w;
   if (t >= a.ntiles) return;
@@ -284,55 +304,60 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
     stat_add(a.stats, kStatSeeds, tot);
     stat_add(a.stats, kStatItems, tot);  // the first frontier
   }
-  (void)flag_reach(a, tr, m, 1);  // round 1 reads parity 1
+  WaveStage st = {stage_mem[w], 16u, 0u};
+  const Next nx = next_frontier(a, 0u);  // round 1's list
+  mark_reach(a, st, nx, tr, m);
+  shard_flush(st, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
 }
 
 template <int CONN>
 __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
-  __shared__ uint32_t flagged;  // this workgroup flagged a tile in this round
+  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ uint32_t cnt[kShards];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
+  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
-  if (threadIdx.x == 0) flagged = 0u;
   uint32_t gen = 0;
   unsigned long long changed = 0, visits = 0;
-  uint32_t rounds = 0;
-  for (uint32_t r = 1;; ++r) {
+  uint32_t r = 1;
+  for (;; ++r) {
+    // Every workgroup reads the same words: nothing writes them between the
+    // previous barrier and this read (round r appends for round r+1).
+    shard_counts(a.counts, r % 3u, a.ntiles, cnt);
+    __syncthreads();
+    uint32_t n = 0;
+    for (int x = 0; x < kShards; ++x) n += cnt[x];
+    if (n == 0u) break;
     if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
     }
+    // The counts of round r+2 are reused: clear them now (they were last read
+    // at the start of round r-1 and are next appended to in round r+1, after
+    // this round's barrier).
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kShards) cstore(shard_count(a.counts, (r + 2u) % 3u, threadIdx.x), 0u);
     const uint32_t* rd = (r & 1u) ? a.feat0 : a.feat1;  // buffer (r-1)&1
     uint32_t* wr = (r & 1u) ? a.feat1 : a.feat0;        // buffer r&1
-    const int par = (int)(r & 1u), npar = 1 - par;
+    const uint32_t par = r & 1u;
+    const uint32_t* lists = a.lists + (size_t)par * kShards * a.ntiles;
     uint32_t* flg = a.flags + (size_t)par * a.ntiles;
-    // This wave's share of the tiles: gw, gw + nw, gw + 2 nw, ...
-    for (uint32_t base = gw; base < a.ntiles; base += nw * (uint32_t)kWave) {
-      const uint32_t mine = base + (uint32_t)lane() * nw;
-      uint64_t mm = ballot(mine < a.ntiles && cload(flg + mine) != 0u);
-      while (mm) {
-        const int b = __ffsll((long long)mm) - 1;
-        mm &= mm - 1;
-        const uint32_t t = base + (uint32_t)b * nw;
-        if (lane() == 0) cstore(flg + t, 0u);
-        const TileRef tr = tile_ref(a, t);
-        load_region(rd, tr, L);
-        uint32_t c = 0;
-        const uint32_t m = relax_tile<CONN>(L, wr, tr, c);
-        changed += c;
-        visits++;
-        if (flag_reach(a, tr, m, npar) && lane() == 0) flagged = 1u;
-        wave_sync();  // LDS is reloaded by the next visit
-      }
+    const Next nx = next_frontier(a, r);
+    for (uint32_t i = gw; i < n; i += nw) {
+      const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
+      if (lane() == 0) cstore(flg + t, 0u);
+      const TileRef tr = tile_ref(a, t);
+      load_region(rd, tr, L);
+      uint32_t c = 0;
+      const uint32_t m = relax_tile<CONN>(L, wr, tr, c);
+      changed += c;
+      visits++;
+      mark_reach(a, s, nx, tr, m);
+      wave_sync();  // LDS is reloaded by the next visit
     }
-    // The barrier also tells whether any workgroup flagged a tile for round r+1.
-    bool more = false;
-    if (!grid_barrier_or(a.bar, gen, a.stats, &flagged, more)) return;
-    if (!more) {
-      rounds = r - 1;  // round r changed nothing; rounds 1..r-1 did
-      break;
-    }
+    shard_flush(s, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
+    if (!grid_barrier(a.bar, gen, a.stats)) return;
   }
   // Both buffers now agree everywhere; write the outputs.
   const uint32_t* fin = a.feat0;
@@ -358,7 +383,8 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
     stat_add(a.stats, kStatUpdates, changed);
     stat_add(a.stats, kStatSweeps, visits);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatRounds, rounds);
+  // Round r found an empty list: round r-1 changed nothing, rounds 1..r-2 did.
+  if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatRounds, r >= 2u ? r - 2u : 0u);
 }
 
 // Image of every global tile, by binary search over the images' first tiles.

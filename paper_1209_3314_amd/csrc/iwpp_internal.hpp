@@ -35,9 +35,10 @@ struct MrArgs {
   uint32_t list_cap;         // capacity of each round's tile list (<= ntiles)
   int32_t max_sweeps;        // sweep iterations per propagation visit before re-listing
   int32_t seed_sweeps;       // sweep iterations per tile in the seed pass
-  uint32_t* flags;           // [2][ntiles] "already listed" per round parity
-  uint32_t* lists;           // [2][ntiles] tile lists per round parity
-  uint32_t* counts;          // [3][64] list fill levels, one per round mod 3 (256 B apart)
+  uint32_t* flags;           // [2][ntiles] tile on the round's list, per round parity
+  uint32_t* lists;           // [2][8 shards][ntiles] tile lists per round parity
+  uint32_t* unsettled;       // [ntiles] the tile's last visit stopped at the sweep cap
+  uint32_t* counts;          // [3 round slots][8 shards][64] list fill levels (256 B apart)
   uint32_t* lost;            // [2][64] a listed tile was dropped (capacity), per parity
   GridBarrier* bar;
   unsigned long long* stats;  // [8 shards][16 fields]
@@ -66,17 +67,17 @@ struct EdtArgs {
   unsigned long long npix;    // total pixels over all images
   uint32_t* feat0;            // [npix] nearest feature (y << 16 | x), ~0 = none; round parity 0
   uint32_t* feat1;            // [npix] round parity 1
-  uint32_t* flags;            // [2][ntiles] tile to visit, per step parity
-  uint32_t* lists;            // unused (kept for the scratch layout)
-  uint32_t* counts;           // [3][64] "some tile is flagged" words of consecutive steps
-  uint32_t* ovf;              // unused
+  uint32_t* flags;            // [2][ntiles] tile on the round's list, per round parity
+  uint32_t* lists;            // [2][8 shards][ntiles] tile lists per round parity
+  uint32_t* counts;           // [3 round slots][8 shards][64] list fill levels (256 B apart)
+  uint32_t* ovf;              // never set: a list holds each tile once
   GridBarrier* bar;
   unsigned long long* stats;
 };
 
 // Bytes of the scratch areas the kernels expect.
 constexpr size_t kBarrierBytes = 4096;
-constexpr size_t kCountsBytes = 3 * 64 * 4;
+constexpr size_t kCountsBytes = 3 * 8 * 64 * 4;
 constexpr size_t kLostBytes = 2 * 64 * 4;
 constexpr size_t kStatsBytes = 8 * 16 * 8;
 

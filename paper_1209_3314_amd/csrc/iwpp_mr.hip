@@ -22,15 +22,17 @@
 // that did not rise was seen with that same value by the neighbour's own
 // sweep, so only risen border pixels can leave a seed across a tile edge.
 //
-// The tile frontier is, by default, a dense array of per-tile flags set by
-// plain stores and scanned by every wave for its share, so building it needs
-// no counter or atomic.  With a capacity, it is instead a bounded work list
-// (the paper's fixed-size global queue, Sec. 3.2): appends are staged per
-// wave in LDS and flushed with one atomic; an append past the capacity is
-// dropped and flagged, and the next round becomes a full round that visits
-// every tile holding a raisable pixel of the current image, which is a valid
-// restart point because every intermediate image is (Sec. 3.2: re-running
-// from a partial output gives the same answer).
+// The tile frontier of a round is a work list split into eight sub-lists, one
+// per group of workgroups (one per XCD): a wave stages its appends in LDS and
+// flushes them with one atomic on its group's counter, a per-tile flag keeps a
+// tile on a round's list once, and the next round splits the concatenated
+// sub-lists evenly over all waves, so a round's visits are balanced.  With a
+// capacity (the paper's fixed-size global queue, Sec. 3.2) the list is one
+// sub-list of that size: an append past it is dropped and flagged, and the
+// next round becomes a full round that visits every tile holding a raisable
+// pixel of the current image, which is a valid restart point because every
+// intermediate image is (Sec. 3.2: re-running from a partial output gives the
+// same answer).
 //
 // The value updates are max-then-min of bytes; the per-tile state is owned by
 // exactly one wave at a time (a tile is on a round's list at most once), so no
@@ -344,18 +346,30 @@ __device__ uint32_t border_marks(const WaveLds& L, uint32_t ot, uint32_t ob, uin
   return m;
 }
 
-// Put tile t on the list of parity `par` from one lane (rare or one-per-wave
-// appends outside the persistent kernel).  A tile past the capacity is
-// dropped and the list's lost flag raised.
-__device__ void list_tile(const MrArgs& a, uint32_t t, int par, uint32_t* count) {
-  if (atomic_or(a.flags + (size_t)par * a.ntiles + t, 1u) != 0u) return;
-  const uint32_t slot = atomic_add(count, 1u);
-  if (slot < a.list_cap) {
-    cstore(a.lists + (size_t)par * a.ntiles + slot, t);
-  } else {
-    cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
-    cstore(a.lost + par * 64, 1u);
+// Can a halo pixel raise a border pixel of the tile?  (Algorithm 5's
+// propagation condition read from the receiving side: J(p) < J(h) and
+// J(p) < I(p), for p on the border and h a halo neighbour of p.)  A tile that
+// was locally stable after its last visit can only have become raisable this
+// way, because only its halo changed since.  Wave-uniform.
+template <int CONN>
+__device__ bool border_raisable(const WaveLds& L) {
+  const int l = lane();
+  bool r = false;
+  // p on row 0 (halo row -1), row T-1 (halo row T), column 0 (halo column -1), column T-1 (halo column T)
+  const uint32_t pt = L.J[lidx(0, l)], it = L.I[lidx(0, l)];
+  const uint32_t pb = L.J[lidx(T - 1, l)], ib = L.I[lidx(T - 1, l)];
+  const uint32_t pl = L.J[lidx(l, 0)], il = L.I[lidx(l, 0)];
+  const uint32_t pr = L.J[lidx(l, T - 1)], ir = L.I[lidx(l, T - 1)];
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    if (CONN == 4 && d != 0) continue;
+    const int c = l + d;  // -1 .. 64: halo corners included
+    r |= pt < umin(L.J[lidx(-1, c)], it);
+    r |= pb < umin(L.J[lidx(T, c)], ib);
+    r |= pl < umin(L.J[lidx(c, -1)], il);
+    r |= pr < umin(L.J[lidx(c, T)], ir);
   }
+  return ballot(r) != 0u;
 }
 
 // ---- raisable-pixel test (full rounds of the bounded mode) -------------------------
@@ -411,65 +425,32 @@ __device__ bool lds_dirty(const WaveLds& L, uint32_t& seeds) {
   return ballot(any) != 0;
 }
 
-// Stage-flush variant for tile work lists: a dropped tile has its flag cleared
-// (so a later mark can list it again) and the list's `lost` flag is raised,
-// which makes a later round rebuild its list by dense detection.
-__device__ void tile_flush(WaveStage& s, uint32_t* list, uint32_t* count, uint32_t cap, uint32_t* flags,
-                           uint32_t* lost) {
-  const uint32_t n = s.n;
-  if (n == 0) return;
-  wave_sync();
-  uint32_t base = 0;
-  if (lane() == 0) base = atomic_add(count, n);
-  base = readlane(base, 0);
-  bool dropped = false;
-  for (uint32_t i = lane(); i < n; i += kWave) {
-    const uint32_t slot = base + i, item = s.items[i];
-    if (slot < cap) {
-      cstore(list + slot, item);
-    } else {
-      cstore(flags + item, 0u);
-      dropped = true;
-    }
-  }
-  if (ballot(dropped) && lane() == 0) cstore(lost, 1u);
-  wave_sync();
-  s.n = 0;
-}
-
-// Put tile `t` (one per lane with pred) on the list of parity `par`, once.
-__device__ __forceinline__ void mark_tiles(const MrArgs& a, WaveStage& s, bool pred, uint32_t t, int par,
-                                           uint32_t* count) {
-  bool fresh = false;
-  if (pred) fresh = atomic_or(a.flags + (size_t)par * a.ntiles + t, 1u) == 0u;
-  const uint64_t m = ballot(fresh);
-  if (m == 0) return;
-  const uint32_t k = (uint32_t)__popcll(m);
-  if (s.n + k > s.cap) tile_flush(s, a.lists + (size_t)par * a.ntiles, count, a.list_cap, a.flags + (size_t)par * a.ntiles,
-                                   a.lost + par * 64);
-  if (fresh) s.items[s.n + mbcnt(m)] = t;
-  s.n += k;
-}
-
 // ---- persistent propagation -----------------------------------------------------------
-// Frontier marks.  Dense mode: a plain store of the tile's flag (whether a
-// round flagged anything travels with the grid barrier).  Bounded mode: a
-// staged list append.  Returns (wave-uniform) whether some lane marked.
-template <bool kBounded>
-__device__ __forceinline__ bool mark(const MrArgs& a, WaveStage& s, bool pred, uint32_t t, int par, uint32_t* word) {
-  if (kBounded) {
-    mark_tiles(a, s, pred, t, par, word);
-  } else if (pred) {
-    cstore(a.flags + (size_t)par * a.ntiles + t, 1u);
-  }
-  return ballot(pred) != 0u;
+// The frontier of round r+1 while round r runs: the parity's flags and list,
+// the sub-list this workgroup appends to, its capacity and lost flag.
+struct Next {
+  uint32_t* flags;
+  uint32_t* list;
+  uint32_t* count;
+  uint32_t cap;
+  uint32_t* lost;
+};
+
+__device__ __forceinline__ Next next_frontier(const MrArgs& a, uint32_t r) {
+  const bool bounded = a.list_cap < a.ntiles;
+  const uint32_t par = (r + 1u) & 1u, shard = bounded ? 0u : (blockIdx.x & (uint32_t)(kShards - 1));
+  Next n;
+  n.flags = a.flags + (size_t)par * a.ntiles;
+  n.list = a.lists + ((size_t)par * kShards + shard) * a.ntiles;
+  n.count = shard_count(a.counts, (r + 1u) % 3u, shard);
+  n.cap = bounded ? a.list_cap : a.ntiles;
+  n.lost = a.lost + par * 64u;
+  return n;
 }
 
 // Flag the neighbours named by border mask m (see border_marks) and, if
-// `unsettled`, the tile itself, for the round of parity `par` (lanes 0..8).
-template <bool kBounded>
-__device__ bool mark_reach(const MrArgs& a, WaveStage& s, const TileRef& tr, uint32_t m, bool unsettled, int par,
-                           uint32_t* word) {
+// `unsettled`, the tile itself, for the next round (lanes 0..8 of the wave).
+__device__ void mark_reach(WaveStage& s, const Next& nx, const TileRef& tr, uint32_t m, bool unsettled) {
   const int l = lane();
   int dy = 0, dx = 0;
   bool want = false;
@@ -481,15 +462,15 @@ __device__ bool mark_reach(const MrArgs& a, WaveStage& s, const TileRef& tr, uin
   } else if (l == 8) {
     want = unsettled;
   }
-  const int ny = tr.ty + dy, nx = tr.tx + dx;
-  want = want && ny >= 0 && ny < tr.j.tiles_y && nx >= 0 && nx < tr.j.tiles_x;
-  return mark<kBounded>(a, s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx), par, word);
+  const int ny = tr.ty + dy, nx_ = tr.tx + dx;
+  want = want && ny >= 0 && ny < tr.j.tiles_y && nx_ >= 0 && nx_ < tr.j.tiles_x;
+  shard_mark(s, want, tr.j.tile_base + (uint32_t)(ny * tr.j.tiles_x + nx_), nx.flags, nx.list, nx.count, nx.cap, nx.lost);
 }
 
 // Round-0 visit: the seed pass of one tile (load from the clamped marker,
 // sweep, write back) and its marks for round 1.
-template <int CONN, bool kBounded>
-__device__ bool seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t, uint32_t* word, uint32_t& iters) {
+template <int CONN>
+__device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next& nx, uint32_t t, uint32_t& iters) {
   const TileRef tr = tile_ref(a, t);
   load_region<true>(tr, L);
   const int l = lane();
@@ -499,20 +480,28 @@ __device__ bool seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t
   const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it);
   iters += it;
   store_tile(tr, L);
+  if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
   const uint32_t m = border_marks<CONN>(L, ot, ob, ol, orr);
-  return mark_reach<kBounded>(a, s, tr, m, !stable, 1, word);
+  mark_reach(s, nx, tr, m, !stable);
 }
 
 // One propagation visit: load the tile and its halo, sweep to local
 // stability, write back, and flag the neighbouring tiles a border change can
-// raise (and the tile itself if the sweep cap stopped it).  With `check`, a
-// tile that has no raisable pixel is left alone.
-template <int CONN, bool kBounded>
-__device__ bool visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t, bool check, int npar,
-                           uint32_t* word, uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
+// raise (and the tile itself if the sweep cap stopped it).  A tile that its
+// last visit left stable needs work only if its new halo can raise its
+// border (`border_raisable`); with `check` (full rounds) the whole tile is
+// tested instead.
+template <int CONN>
+__device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next& nx, uint32_t t, bool check,
+                           uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
   const TileRef tr = tile_ref(a, t);
   load_region<false>(tr, L);
-  if (check && !lds_dirty<CONN>(L, seeds)) return false;
+  if (check) {
+    if (!lds_dirty<CONN>(L, seeds)) return;
+  } else {
+    const bool was_unsettled = readlane(lane() == 0 ? cload(a.unsettled + t) : 0u, 0) != 0u;
+    if (!was_unsettled && !border_raisable<CONN>(L)) return;
+  }
   const int l = lane();
   const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
@@ -520,121 +509,88 @@ __device__ bool visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, uint32_t t
   const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it);
   iters += it;
   visits++;
+  if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
   // A visit that ends within its first iteration changed nothing; one that
   // ends later (or is cut off) changed something.
   const bool changed = it > 1 || !stable;
   if (changed) store_tile(tr, L);
   const uint32_t m = changed ? border_marks<CONN>(L, ot, ob, ol, orr) : 0u;
-  return mark_reach<kBounded>(a, s, tr, m, !stable, npar, word);
+  mark_reach(s, nx, tr, m, !stable);
 }
 
 // Round 0 is the seed pass over every tile; round r >= 1 visits the tiles
-// flagged in round r-1 and flags the tiles of round r+1 (parity (r+1)&1,
-// word or count slot (r+1)%3).  Bounded mode: a round whose list lost tiles
-// to the capacity is replaced by a full round that visits every tile holding
-// a raisable pixel (all flags cleared first), restarting from the current
-// image.  The flags must be zero when the kernel starts.
-template <int CONN, bool kBounded>
+// listed in round r-1 and lists the tiles of round r+1 (parity (r+1)&1,
+// count slot (r+1)%3).  The list is split over kShards sub-lists, one per
+// group of workgroups, and consumed evenly by all waves.  Bounded mode (a
+// capacity below the tile count) uses one sub-list of that capacity; a round
+// whose list lost tiles is replaced by a full round that visits every tile
+// holding a raisable pixel (all flags cleared first), restarting from the
+// current image.  The flags and the counts must be zero when the kernel starts.
+template <int CONN>
 __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kBounded ? kStageCap : 1];
-  __shared__ uint32_t decision[2];
-  __shared__ uint32_t flagged;  // dense mode: this workgroup flagged a tile in this round
+  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+  __shared__ uint32_t cnt[kShards];
+  __shared__ uint32_t lost_sh;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
-  WaveStage s = {stage_mem[w], kBounded ? (uint32_t)kStageCap : 1u, 0u};
+  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
-  if (threadIdx.x == 0) flagged = 0u;
+  const uint32_t cap = a.list_cap < a.ntiles ? a.list_cap : a.ntiles;
   uint32_t gen = 0;
   uint32_t visits = 0, iters = 0, seed_iters = 0, rounds = 0, restarts = 0, seeds = 0, first = 0;
-  bool ok = true, more = true;
   {
-    uint32_t* word = a.counts + 64u;  // bounded mode: round 1 reads count slot 1
-    for (uint32_t t = gw; t < a.ntiles; t += nw)
-      if (seed_visit<CONN, kBounded>(a, L, s, t, word, seed_iters) && !kBounded && lane() == 0) flagged = 1u;
-    if (kBounded) {
-      tile_flush(s, a.lists + a.ntiles, word, a.list_cap, a.flags + a.ntiles, a.lost + 64);
-      ok = grid_barrier(a.bar, gen, a.stats);
-    } else {
-      ok = grid_barrier_or(a.bar, gen, a.stats, &flagged, more);
-    }
+    const Next nx = next_frontier(a, 0u);
+    for (uint32_t t = gw; t < a.ntiles; t += nw) seed_visit<CONN>(a, L, s, nx, t, seed_iters);
+    shard_flush(s, nx.list, nx.count, nx.cap, nx.flags, nx.lost);
   }
+  bool ok = grid_barrier(a.bar, gen, a.stats);
   for (uint32_t r = 1; ok; ++r) {
-    const int par = (int)(r & 1u), npar = 1 - par;
+    const uint32_t par = r & 1u;
+    // Every workgroup reads the same words: nothing writes them between the
+    // previous barrier and this read (round r appends for round r+1).
+    shard_counts(a.counts, r % 3u, cap, cnt);
+    if (threadIdx.x == 0) lost_sh = cload(a.lost + par * 64u);
+    __syncthreads();
     uint32_t n = 0;
-    bool full = false;
-    if (kBounded) {
-      // Every workgroup reads the same words: nothing writes them between the
-      // previous barrier and this read (round r appends for round r+1).
-      if (threadIdx.x == 0) {
-        decision[0] = cload(a.counts + (r % 3u) * 64u);
-        decision[1] = cload(a.lost + par * 64);
-      }
-      __syncthreads();
-      n = decision[0];
-      full = decision[1] != 0u;
-      if (!full && n == 0u) break;
-    } else if (!more) {
-      break;
-    }
+    for (int x = 0; x < kShards; ++x) n += cnt[x];
+    const bool full = lost_sh != 0u;
+    if (!full && n == 0u) break;
     if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
     }
+    if (full) {
+      if (!grid_barrier(a.bar, gen, a.stats)) break;  // everyone has read the decision
+      for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2u * a.ntiles; i += gridDim.x * blockDim.x)
+        cstore(a.flags + i, 0u);
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cstore(a.lost, 0u);
+        cstore(a.lost + 64, 0u);
+        restarts++;
+      }
+      if (!grid_barrier(a.bar, gen, a.stats)) break;
+    }
+    // The counts of round r+2 are reused: clear them now (they were last read
+    // in round r-1, and are next appended to in round r+1, after this round's barrier).
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kShards) cstore(shard_count(a.counts, (r + 2u) % 3u, threadIdx.x), 0u);
+    const Next nx = next_frontier(a, r);
     const uint32_t before = visits;
-    if (kBounded) {
-      if (full) {
-        if (!grid_barrier(a.bar, gen, a.stats)) break;  // everyone has read the decision
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < 2u * a.ntiles; i += gridDim.x * blockDim.x)
-          cstore(a.flags + i, 0u);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-          cstore(a.lost, 0u);
-          cstore(a.lost + 64, 0u);
-          restarts++;
-        }
-        if (!grid_barrier(a.bar, gen, a.stats)) break;
-      }
-      // The count of round r+2 is reused: clear it now (it was last read in
-      // round r-1, and is next appended to in round r+1, after this round's barrier).
-      if (blockIdx.x == 0 && threadIdx.x == 0) cstore(a.counts + ((r + 2u) % 3u) * 64u, 0u);
-      uint32_t* word = a.counts + ((r + 1u) % 3u) * 64u;
-      if (full) {
-        for (uint32_t t = gw; t < a.ntiles; t += nw)
-          visit_tile<CONN, kBounded>(a, L, s, t, true, npar, word, visits, iters, seeds);
-      } else {
-        if (n > a.list_cap) n = a.list_cap;
-        const uint32_t* list = a.lists + (size_t)par * a.ntiles;
-        for (uint32_t i = gw; i < n; i += nw) {
-          const uint32_t t = cload(list + i);
-          if (lane() == 0) cstore(a.flags + (size_t)par * a.ntiles + t, 0u);
-          visit_tile<CONN, kBounded>(a, L, s, t, false, npar, word, visits, iters, seeds);
-        }
-      }
-      tile_flush(s, a.lists + (size_t)npar * a.ntiles, word, a.list_cap, a.flags + (size_t)npar * a.ntiles,
-                 a.lost + npar * 64);
+    if (full) {
+      for (uint32_t t = gw; t < a.ntiles; t += nw) visit_tile<CONN>(a, L, s, nx, t, true, visits, iters, seeds);
     } else {
-      // This wave's share of the tiles: gw, gw + nw, gw + 2 nw, ...
+      const uint32_t* lists = a.lists + (size_t)par * kShards * a.ntiles;
       uint32_t* flg = a.flags + (size_t)par * a.ntiles;
-      for (uint32_t base = gw; base < a.ntiles; base += nw * (uint32_t)kWave) {
-        const uint32_t mine = base + (uint32_t)lane() * nw;
-        uint64_t mm = ballot(mine < a.ntiles && cload(flg + mine) != 0u);
-        while (mm) {
-          const int b = __ffsll((long long)mm) - 1;
-          mm &= mm - 1;
-          const uint32_t t = base + (uint32_t)b * nw;
-          if (lane() == 0) cstore(flg + t, 0u);
-          if (visit_tile<CONN, kBounded>(a, L, s, t, false, npar, nullptr, visits, iters, seeds) && lane() == 0)
-            flagged = 1u;
-        }
+      for (uint32_t i = gw; i < n; i += nw) {
+        const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
+        if (lane() == 0) cstore(flg + t, 0u);
+        visit_tile<CONN>(a, L, s, nx, t, false, visits, iters, seeds);
       }
     }
+    shard_flush(s, nx.list, nx.count, nx.cap, nx.flags, nx.lost);
     if (r == 1) first = visits - before;
     rounds++;
-    if (kBounded) {
-      if (!grid_barrier(a.bar, gen, a.stats)) break;
-    } else {
-      if (!grid_barrier_or(a.bar, gen, a.stats, &flagged, more)) break;
-    }
+    ok = grid_barrier(a.bar, gen, a.stats);
   }
   if (lane() == 0) {
     stat_add(a.stats, kStatSeeds, (unsigned long long)first);
@@ -676,9 +632,7 @@ int mr_launch(const MrArgs& a, int conn, int persistent_blocks, hipStream_t stre
     *err = "flag reset launch failed";
     return -1;
   }
-  const bool bounded = a.list_cap < a.ntiles;
-  void* fn = conn == 8 ? (bounded ? reinterpret_cast<void*>(&k_propagate<8, true>) : reinterpret_cast<void*>(&k_propagate<8, false>))
-                       : (bounded ? reinterpret_cast<void*>(&k_propagate<4, true>) : reinterpret_cast<void*>(&k_propagate<4, false>));
+  void* fn = conn == 8 ? reinterpret_cast<void*>(&k_propagate<8>) : reinterpret_cast<void*>(&k_propagate<4>);
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) {
