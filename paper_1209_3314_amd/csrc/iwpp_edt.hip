@@ -12,20 +12,26 @@
 // (lexicographic: squared distance, then feature index) and the result does
 // not depend on thread order.
 //
-// How.  The image is cut into 32x32 tiles.  A round visits only the tiles
-// whose pixels or one-pixel halo changed in the previous round: one wave loads
-// the tile and its halo from the previous round's buffer into LDS, recomputes
-// every pixel of the tile with the operator above, writes the tile to the other
-// buffer, and flags itself and the neighbouring tiles its changes can reach for
-// the next round.  Nothing writes the buffer a round reads, so no atomics touch
-// pixels.  A tile that is not visited in a round keeps equal values in both
-// buffers: a tile changes only in rounds it is visited, and after a round in
-// which it changed it is visited again, so it stops being visited only after a
-// round in which it (re)wrote its unchanged values.  The tiles of a round are
-// a work list split into eight sub-lists, one per group of workgroups (one
-// per XCD), appended to with one atomic per wave flush and consumed evenly by
-// all waves in the next round; a per-tile flag keeps a tile on a round's list
-// once.
+// How: K rounds per tile visit (temporal blocking).  The image is cut into
+// 26x26 tiles.  A visit loads a tile with a K-pixel halo (a 34x34 region) from
+// the state after round r into LDS and applies the operator K times, each time
+// on a region one pixel smaller on every side, which leaves the tile exactly
+// at round r + K; the tile goes to the other state buffer.  One step of the
+// persistent kernel visits the listed tiles and ends in one grid barrier, so
+// K rounds cost one barrier.  Which tiles a step must visit follows from two
+// facts: a pixel's value only improves (its own previous feature is always a
+// candidate), and a change travels at most one pixel per round.  So a tile can
+// change during a step only if some pixel within K pixels of it changed in
+// the last round of the previous step; such a change lists the tile that
+// holds it and the neighbours within reach.  A tile that changed at all during
+// a step is listed again, so that it rewrites its (then settled) values into
+// the other buffer: a tile that is not visited holds equal values in both
+// buffers, and every pixel a visit reads is at round r.
+//
+// The tiles of a step are a work list split into eight sub-lists, one per
+// group of workgroups (one per XCD), appended to with one atomic per wave
+// flush and consumed evenly by all waves in the next step; a per-tile flag
+// keeps a tile on a step's list once.
 //
 // State is the feature's packed coordinates (y << 16 | x), 4 bytes per pixel.
 // A candidate's squared distance is one saturating packed 16-bit subtraction
@@ -39,17 +45,24 @@
 namespace iwpp {
 namespace edt {
 
-constexpr int TE = kEdtTile;      // tile side
-constexpr int RP = TE + 2;        // region side with the halo
+constexpr int K = kEdtHalo;        // rounds per step = halo width
+constexpr int TE = kEdtTile;       // tile side
+constexpr int RP = TE + 2 * K;     // region side
+constexpr int kCPR = (RP + 3) / 4; // 16-byte chunks per region row
+constexpr int PE = 4 * kCPR;       // LDS row pitch (words)
 constexpr int kWavesPerBlock = 4;
-constexpr int kStageCap = 128;
+constexpr int kStageCap = 32;
 constexpr uint32_t kNone = 0x80008000u;
-constexpr uint32_t kMaxRounds = 1u << 20;
+constexpr uint32_t kMaxSteps = (1u << 20) / K;
+static_assert(RP - 2 <= 32, "a round's region row must fit 32 lanes");
+static_assert(K % 4 == 0 || K < 4, "region chunks must not straddle the image's left edge");
+static_assert(K <= TE, "a change must reach no farther than the neighbouring tiles");
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 typedef short s2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pack_yx(int y, int x) { return ((uint32_t)y << 16) | (uint32_t)x; }
+__device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
 // Squared distance between packed points q and f (0 <= coordinates < 32767
 // for q; f real or kNone).
@@ -86,39 +99,35 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const uint32_t* base
   return make_rsrc(base + j.pix_base + (unsigned long long)row0 * (uint32_t)j.w, (uint32_t)rows * (uint32_t)j.w * 4u + pad);
 }
 
-// Region in LDS: 34 rows; row pitch 40 words, tile column x at word 4 + x
-// (the halo at words 3 and 36), so that a row is ten aligned 16-byte chunks
-// starting at tile column -4.
-constexpr int PE = 40;
-constexpr int kC0 = 4;
-struct WaveLds {
-  uint32_t F[RP * PE];
-};
-
 // Offset that makes a raw buffer access fall outside every buffer (reads 0).
 constexpr uint32_t kOutside = 0xFFFFFFF0u;
 constexpr uint32_t kStatePad = 16u;  // readable bytes after the last pixel of a state buffer
 static_assert(kStatePad <= kEdtStatePad, "state buffers must be padded");
 
-// Load the tile of `src` and its halo into LDS (kNone outside the image).
-// 34 rows x 10 chunks of four words, six per lane, all as 16-byte loads with
-// no branches between them, so the wave waits for memory once per visit.
-// Chunks reaching outside the image are loaded anyway (or pointed outside the
-// buffer) and their outside words replaced by kNone.
-__device__ void load_region(const uint32_t* src, const TileRef& tr, WaveLds& L) {
+// Two region buffers per wave (the rounds of a visit alternate between them).
+struct WaveLds {
+  uint32_t F[2][RP * PE];
+};
+
+// Load the region of tile tr (rows and columns from K before the tile) from
+// `src` into S; pixels outside the image read as kNone.  kCPR 16-byte chunks
+// per row, all issued with no branch in between so the wave waits for memory
+// once; a chunk cut by the image's right edge is loaded whole (the state
+// buffers are padded) and its outside words replaced.
+__device__ void load_region(const uint32_t* src, const TileRef& tr, uint32_t* S) {
   const EdtJob& j = tr.j;
-  const int y0 = tr.ty * TE, x0 = tr.tx * TE;
-  const int row0 = y0 > 0 ? y0 - 1 : 0;
-  const int row1 = y0 + TE + 1 < j.h ? y0 + TE + 1 : j.h;
+  const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
+  const int row0 = ry0 > 0 ? ry0 : 0;
+  const int row1 = ry0 + RP < j.h ? ry0 + RP : j.h;
   const __amdgpu_buffer_rsrc_t rs = rows_rsrc(src, j, row0, row1 - row0, kStatePad);
-  constexpr int kChunks = RP * 10;
+  constexpr int kChunks = RP * kCPR;
   constexpr int kPer = (kChunks + kWave - 1) / kWave;
   v4u v[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int idx = lane() + k * kWave;
-    const int ry = idx / 10, c = idx - ry * 10;
-    const int y = y0 - 1 + ry, xs = x0 - kC0 + 4 * c;
+    const int ry = idx / kCPR, c = idx - ry * kCPR;
+    const int y = ry0 + ry, xs = rx0 + 4 * c;
     const bool ok = idx < kChunks && y >= 0 && y < j.h && xs >= 0 && xs < j.w;
     const uint32_t off = ok ? ((uint32_t)(y - row0) * (uint32_t)j.w + (uint32_t)xs) * 4u : kOutside;
     v[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kSc1));
@@ -126,108 +135,125 @@ __device__ void load_region(const uint32_t* src, const TileRef& tr, WaveLds& L) 
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int idx = lane() + k * kWave;
-    const int ry = idx / 10, c = idx - ry * 10;
-    const int y = y0 - 1 + ry, xs = x0 - kC0 + 4 * c;
+    const int ry = idx / kCPR, c = idx - ry * kCPR;
+    const int y = ry0 + ry, xs = rx0 + 4 * c;
     const bool row_ok = y >= 0 && y < j.h;
     v4u o;
 #pragma unroll
     for (int b = 0; b < 4; ++b) o[b] = (row_ok && xs + b >= 0 && xs + b < j.w) ? v[k][b] : kNone;
-    if (idx < kChunks) *reinterpret_cast<v4u*>(&L.F[ry * PE + 4 * c]) = o;
+    if (idx < kChunks) *reinterpret_cast<v4u*>(&S[ry * PE + 4 * c]) = o;
   }
   wave_sync();
 }
 
-// One round of the operator on the tile in LDS.  Lane l handles column l & 31
-// of rows (l >> 5), (l >> 5) + 2, ...; the new values go to `dst` (the other
-// buffer), unconditionally.  Returns a bit mask of where something changed:
-// bit 0 anywhere, 1 row 0, 2 last row, 3 column 0, 4 last column, 5..8 the
-// corners (top-left, top-right, bottom-left, bottom-right); `changed` counts
-// the changed pixels.
-template <int CONN>
-__device__ uint32_t relax_tile(const WaveLds& L, uint32_t* dst, const TileRef& tr, uint32_t& changed) {
-  const EdtJob& j = tr.j;
-  const int y0 = tr.ty * TE, x0 = tr.tx * TE;
-  const int x = lane() & (TE - 1), yb = lane() >> 5;
-  const int qx = x0 + x;
-  const int row0 = y0 > 0 ? y0 - 1 : 0;
-  const int row1 = y0 + TE + 1 < j.h ? y0 + TE + 1 : j.h;
-  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(dst, j, row0, row1 - row0);
-  uint32_t any = 0, n = 0;
-#pragma unroll 4
-  for (int k = 0; k < TE / 2; ++k) {
-    const int y = yb + 2 * k;
-    const int qy = y0 + y;
-    const uint32_t q = pack_yx(qy, qx);
-    const uint32_t* c = &L.F[(y + 1) * PE + kC0 + x];
-    const uint32_t old = c[0];
-    unsigned long long best = ((unsigned long long)d2(q, old) << 32) | old;
-    offer(q, c[-PE], best);
-    offer(q, c[PE], best);
-    offer(q, c[-1], best);
-    offer(q, c[1], best);
-    if (CONN == 8) {
-      offer(q, c[-PE - 1], best);
-      offer(q, c[-PE + 1], best);
-      offer(q, c[PE - 1], best);
-      offer(q, c[PE + 1], best);
-    }
-    const uint32_t bf = (uint32_t)best;
-    const bool inside = qy < j.h && qx < j.w;
-    if (inside)
-      __builtin_amdgcn_raw_buffer_store_b32(bf, rs, ((uint32_t)(qy - row0) * (uint32_t)j.w + (uint32_t)qx) * 4u, 0, kSc1);
-    if (inside && bf != old) {
-      n++;
-      any |= 1u;
-      if (y == 0) any |= 2u;
-      if (y == TE - 1) any |= 4u;
-      if (x == 0) any |= 8u;
-      if (x == TE - 1) any |= 16u;
-      if (y == 0 && x == 0) any |= 32u;
-      if (y == 0 && x == TE - 1) any |= 64u;
-      if (y == TE - 1 && x == 0) any |= 128u;
-      if (y == TE - 1 && x == TE - 1) any |= 256u;
-    }
-  }
-  changed += n;
-  uint32_t m = 0;
-#pragma unroll
-  for (int b = 0; b < 9; ++b)
-    if (ballot((any >> b) & 1u)) m |= 1u << b;
-  return m;
+// Zone bits of a tile pixel (cy, cx): which neighbouring tiles lie within K
+// pixels of it -- 1 top, 2 bottom, 3 left, 4 right, 5 top-left, 6 top-right,
+// 7 bottom-left, 8 bottom-right (bit 0, the tile itself, is set by callers).
+__device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
+  const bool t = cy < K, b = cy >= TE - K, l = cx < K, r = cx >= TE - K;
+  return (t ? 2u : 0u) | (b ? 4u : 0u) | (l ? 8u : 0u) | (r ? 16u : 0u) | (t && l ? 32u : 0u) |
+         (t && r ? 64u : 0u) | (b && l ? 128u : 0u) | (b && r ? 256u : 0u);
 }
 
-// The list of round r+1 while round r runs (r = 0 for the initial frontier):
-// the parity's flags and the sub-list of this workgroup's group.
+// K rounds of the operator on the region in LDS, F[0] -> F[1] -> F[0] ...
+// Round i computes region rows and columns [i, RP-i) from round i-1's values;
+// lane l handles column i + (l & 31) of rows i + (l >> 5), + 2, ...  Pixels
+// outside the image stay none.  Accumulates the changed tile pixels (over
+// the rounds), the zone mask (bit 0: a tile pixel changed; bits 1..8: a
+// change in round K within K pixels of that side) and the last round (1..K)
+// with a change.  The result is left in F[K & 1].
+template <int CONN>
+__device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, uint32_t& zone, uint32_t& last) {
+  const EdtJob& j = tr.j;
+  const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
+  const int x = lane() & 31, yb = lane() >> 5;
+#pragma unroll 1
+  for (int i = 1; i <= K; ++i) {
+    const uint32_t* src = L.F[(i - 1) & 1];
+    uint32_t* dst = L.F[i & 1];
+    const int col = i + x;
+    const int qx = rx0 + col;
+    const bool col_act = col < RP - i;
+    const bool col_in = qx >= 0 && qx < j.w;
+    const bool col_tile = col >= K && col < K + TE;
+#pragma unroll 2
+    for (int row = i + yb; row < RP - i; row += 2) {
+      if (!col_act) continue;
+      const int qy = ry0 + row;
+      const uint32_t q = pack_yx(qy, qx);
+      const uint32_t* c = &src[row * PE + col];
+      const uint32_t old = c[0];
+      unsigned long long best = ((unsigned long long)d2(q, old) << 32) | old;
+      offer(q, c[-PE], best);
+      offer(q, c[PE], best);
+      offer(q, c[-1], best);
+      offer(q, c[1], best);
+      if (CONN == 8) {
+        offer(q, c[-PE - 1], best);
+        offer(q, c[-PE + 1], best);
+        offer(q, c[PE - 1], best);
+        offer(q, c[PE + 1], best);
+      }
+      const bool inside = col_in && qy >= 0 && qy < j.h;
+      const uint32_t nv = inside ? (uint32_t)best : kNone;
+      dst[row * PE + col] = nv;
+      if (inside && col_tile && row >= K && row < K + TE && nv != old) {
+        changed++;
+        last = (uint32_t)i;
+        zone |= 1u;
+        if (i == K) zone |= zone_bits(row - K, col - K);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Store the tile (region rows and columns [K, K + TE)) from S to `dst`.
+__device__ void store_tile(const uint32_t* S, uint32_t* dst, const TileRef& tr) {
+  const EdtJob& j = tr.j;
+  const int y0 = tr.ty * TE, x0 = tr.tx * TE;
+  const int row1 = y0 + TE < j.h ? y0 + TE : j.h;
+  const __amdgpu_buffer_rsrc_t rs = rows_rsrc(dst, j, y0, row1 - y0);
+  for (int idx = lane(); idx < TE * TE; idx += kWave) {
+    const int cy = idx / TE, cx = idx - cy * TE;
+    const int y = y0 + cy, x = x0 + cx;
+    if (y < j.h && x < j.w)
+      __builtin_amdgcn_raw_buffer_store_b32(S[(cy + K) * PE + cx + K], rs,
+                                            ((uint32_t)cy * (uint32_t)j.w + (uint32_t)x) * 4u, 0, kSc1);
+  }
+}
+
+// The list of step m+1 while step m runs (m = 0 for the initial list): the
+// parity's flags and the sub-list of this workgroup's group.
 struct Next {
   uint32_t* flags;
   uint32_t* list;
   uint32_t* count;
 };
 
-__device__ __forceinline__ Next next_frontier(const EdtArgs& a, uint32_t r) {
-  const uint32_t par = (r + 1u) & 1u, shard = blockIdx.x & (uint32_t)(kShards - 1);
+__device__ __forceinline__ Next next_frontier(const EdtArgs& a, uint32_t m) {
+  const uint32_t par = (m + 1u) & 1u, shard = blockIdx.x & (uint32_t)(kShards - 1);
   Next n;
   n.flags = a.flags + (size_t)par * a.ntiles;
   n.list = a.lists + ((size_t)par * kShards + shard) * a.ntiles;
-  n.count = shard_count(a.counts, (r + 1u) % 3u, shard);
+  n.count = shard_count(a.counts, (m + 1u) % 3u, shard);
   return n;
 }
 
-// List, for the next round, the tiles that the changes of tile tr (mask m of
-// relax_tile, or of the initial state) reach: itself (bit 0) and each
-// neighbour whose halo holds a changed pixel.  Lanes 0..8 of the wave each
+// List, for the next step, the tiles named by zone mask z of tile tr: itself
+// (bit 0) and the neighbours of bits 1..8.  Lanes 0..8 of the wave each
 // handle one candidate.
 __device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const Next& nx, const TileRef& tr,
-                                           uint32_t m) {
+                                           uint32_t z) {
   const int l = lane();
   int dy = 0, dx = 0;
   bool want = false;
   if (l == 0) {
-    want = (m & 1u) != 0u;
+    want = (z & 1u) != 0u;
   } else if (l <= 8) {
     // lanes 1..8: top, bottom, left, right, top-left, top-right, bottom-left, bottom-right
     const int k = l - 1;
-    want = (m & (k < 4 ? (2u << k) : (32u << (k - 4)))) != 0u;
+    want = (z & (k < 4 ? (2u << k) : (32u << (k - 4)))) != 0u;
     dy = k == 0 ? -1 : (k == 1 ? 1 : (k < 4 ? 0 : (k < 6 ? -1 : 1)));
     dx = k < 2 ? 0 : (k == 2 ? -1 : (k == 3 ? 1 : ((k & 1) ? 1 : -1)));
   }
@@ -239,14 +265,15 @@ __device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const
 
 // Initial state (features carry themselves, everything else none) in both
 // buffers, the contour-feature count (Algorithm 6's initial queue), and the
-// first round's list: the tiles holding a non-feature pixel next to a
-// feature (exactly the pixels round 1 changes) and the neighbours whose halo
-// holds one.  One wave per tile; the binary region is staged in LDS.  The
-// flags and counts must be zero beforehand.
+// first step's list: round 1 changes exactly the non-features next to a
+// feature, so their tiles and the neighbours within K pixels are listed.  One
+// wave per tile; the binary region (tile and one-pixel halo) is staged in
+// LDS.  The flags and counts must be zero beforehand.
 template <int CONN>
 __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
-  constexpr int BP = RP + 2;  // byte pitch
-  __shared__ uint8_t binl[kWavesPerBlock][RP * BP];
+  constexpr int BR = TE + 2;  // binary region side
+  constexpr int BP = BR + 2;  // byte pitch
+  __shared__ uint8_t binl[kWavesPerBlock][BR * BP];
   __shared__ uint32_t stage_mem[kWavesPerBlock][16];
   const int w = threadIdx.x / kWave;
   const uint32_t t = blockIdx.x * kWavesPerBlock + w;
@@ -256,19 +283,18 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   const int y0 = tr.ty * TE, x0 = tr.tx * TE;
   uint8_t* B = binl[w];
   // Region bytes: 1 = feature, 0 = other or outside the image.
-  for (int idx = lane(); idx < RP * RP; idx += kWave) {
-    const int ry = idx / RP, rx = idx - ry * RP;
+  for (int idx = lane(); idx < BR * BR; idx += kWave) {
+    const int ry = idx / BR, rx = idx - ry * BR;
     const int y = y0 - 1 + ry, x = x0 - 1 + rx;
     B[ry * BP + rx] = (y >= 0 && y < j.h && x >= 0 && x < j.w && j.bin[(size_t)y * (uint32_t)j.w + (uint32_t)x] == 0) ? 1 : 0;
   }
   wave_sync();
-  const int x = lane() & (TE - 1), yb = lane() >> 5;
+  const int x = lane() & 31, yb = lane() >> 5;
   const int qx = x0 + x;
-  uint32_t contour = 0, any = 0;
-  for (int k = 0; k < TE / 2; ++k) {
-    const int y = yb + 2 * k;
+  uint32_t contour = 0, zone = 0;
+  for (int y = yb; y < TE; y += 2) {
     const int qy = y0 + y;
-    if (qy >= j.h || qx >= j.w) continue;
+    if (x >= TE || qy >= j.h || qx >= j.w) continue;
     const uint8_t* c = &B[(y + 1) * BP + x + 1];
     const bool feat = c[0] != 0;
     int nf = c[-BP] + c[BP] + c[-1] + c[1];
@@ -282,31 +308,21 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
     a.feat0[p] = v;
     a.feat1[p] = v;
     contour += (feat && nf < nin) ? 1u : 0u;  // a feature with a non-feature neighbour
-    if (!feat && nf > 0) {
-      any |= 1u;
-      if (y == 0) any |= 2u;
-      if (y == TE - 1) any |= 4u;
-      if (x == 0) any |= 8u;
-      if (x == TE - 1) any |= 16u;
-      if (y == 0 && x == 0) any |= 32u;
-      if (y == 0 && x == TE - 1) any |= 64u;
-      if (y == TE - 1 && x == 0) any |= 128u;
-      if (y == TE - 1 && x == TE - 1) any |= 256u;
-    }
+    if (!feat && nf > 0) zone |= 1u | zone_bits(y, x);
   }
   uint32_t tot = contour;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-  uint32_t m = 0;
+  uint32_t z = 0;
 #pragma unroll
   for (int b = 0; b < 9; ++b)
-    if (ballot((any >> b) & 1u)) m |= 1u << b;
+    if (ballot((zone >> b) & 1u)) z |= 1u << b;
   if (lane() == 0) {
     stat_add(a.stats, kStatSeeds, tot);
     stat_add(a.stats, kStatItems, tot);  // the first frontier
   }
   WaveStage st = {stage_mem[w], 16u, 0u};
-  const Next nx = next_frontier(a, 0u);  // round 1's list
-  mark_reach(a, st, nx, tr, m);
+  const Next nx = next_frontier(a, 0u);  // step 1's list
+  mark_reach(a, st, nx, tr, z);
   shard_flush(st, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
 }
 
@@ -315,45 +331,55 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
   __shared__ uint32_t cnt[kShards];
+  __shared__ uint32_t last_sh;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
   WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
+  if (threadIdx.x == 0) last_sh = 0u;
   uint32_t gen = 0;
   unsigned long long changed = 0, visits = 0;
-  uint32_t r = 1;
-  for (;; ++r) {
+  uint32_t last_round = 0;  // this wave's last round with a change
+  for (uint32_t m = 1;; ++m) {
     // Every workgroup reads the same words: nothing writes them between the
-    // previous barrier and this read (round r appends for round r+1).
-    shard_counts(a.counts, r % 3u, a.ntiles, cnt);
+    // previous barrier and this read (step m appends for step m+1).
+    shard_counts(a.counts, m % 3u, a.ntiles, cnt);
     __syncthreads();
     uint32_t n = 0;
     for (int x = 0; x < kShards; ++x) n += cnt[x];
     if (n == 0u) break;
-    if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
+    if (m >= kMaxSteps) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
     }
-    // The counts of round r+2 are reused: clear them now (they were last read
-    // at the start of round r-1 and are next appended to in round r+1, after
-    // this round's barrier).
-    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kShards) cstore(shard_count(a.counts, (r + 2u) % 3u, threadIdx.x), 0u);
-    const uint32_t* rd = (r & 1u) ? a.feat0 : a.feat1;  // buffer (r-1)&1
-    uint32_t* wr = (r & 1u) ? a.feat1 : a.feat0;        // buffer r&1
-    const uint32_t par = r & 1u;
+    // The counts of step m+2 are reused: clear them now (they were last read
+    // at the start of step m-1 and are next appended to in step m+1, after
+    // this step's barrier).
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kShards) cstore(shard_count(a.counts, (m + 2u) % 3u, threadIdx.x), 0u);
+    const uint32_t* rd = (m & 1u) ? a.feat0 : a.feat1;  // buffer (m-1)&1
+    uint32_t* wr = (m & 1u) ? a.feat1 : a.feat0;        // buffer m&1
+    const uint32_t par = m & 1u;
     const uint32_t* lists = a.lists + (size_t)par * kShards * a.ntiles;
     uint32_t* flg = a.flags + (size_t)par * a.ntiles;
-    const Next nx = next_frontier(a, r);
+    const Next nx = next_frontier(a, m);
     for (uint32_t i = gw; i < n; i += nw) {
       const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
       if (lane() == 0) cstore(flg + t, 0u);
       const TileRef tr = tile_ref(a, t);
-      load_region(rd, tr, L);
-      uint32_t c = 0;
-      const uint32_t m = relax_tile<CONN>(L, wr, tr, c);
+      load_region(rd, tr, L.F[0]);
+      uint32_t c = 0, zone = 0, lr = 0;
+      relax_steps<CONN>(L, tr, c, zone, lr);
       changed += c;
       visits++;
-      mark_reach(a, s, nx, tr, m);
+      uint32_t z = 0;
+#pragma unroll
+      for (int b = 0; b < 9; ++b)
+        if (ballot((zone >> b) & 1u)) z |= 1u << b;
+      uint32_t lw = lr;
+      for (int o = 32; o > 0; o >>= 1) lw = umax32(lw, (uint32_t)__shfl_xor((int)lw, o));
+      if (lw) last_round = umax32(last_round, (m - 1u) * (uint32_t)K + lw);
+      store_tile(L.F[K & 1], wr, tr);
+      mark_reach(a, s, nx, tr, z);
       wave_sync();  // LDS is reloaded by the next visit
     }
     shard_flush(s, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
@@ -382,9 +408,12 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
     stat_add(a.stats, kStatItems, changed);  // pixels changed in a round join the next frontier
     stat_add(a.stats, kStatUpdates, changed);
     stat_add(a.stats, kStatSweeps, visits);
+    atomicMax(&last_sh, last_round);
   }
-  // Round r found an empty list: round r-1 changed nothing, rounds 1..r-2 did.
-  if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatRounds, r >= 2u ? r - 2u : 0u);
+  __syncthreads();
+  // Rounds: the last round in which any pixel changed -- a maximum, kept in
+  // shard 0 so that the host's sum over the shards leaves it unchanged.
+  if (threadIdx.x == 0 && last_sh) atomic_max(a.stats + kStatRounds, (unsigned long long)last_sh);
 }
 
 // Image of every global tile, by binary search over the images' first tiles.

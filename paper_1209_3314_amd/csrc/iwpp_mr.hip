@@ -270,34 +270,41 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint3
   wave_sync();
 }
 
-// Sweep the tile in LDS until a full raster + anti-raster iteration changes
-// nothing, or `max_it` iterations.  One iteration is the four axis scans of
-// Algorithm 5 in its order: row-wise forward (N^{+,0}), column-wise forward
-// (N^{0,+}), row-wise backward (N^{-,0}), column-wise backward (N^{0,-}).
-// Every step is one elementary update J(p) <- max(J(p), J(q in the scan's
-// neighbour set)) ^ I(p), so the tile never leaves [J ^ I, rho_I(J)].  Halo
-// pixels are sources only.  Returns true if the tile is locally stable.
+// Sweep the tile in LDS until it is locally stable, or `max_it` iterations.
+// One iteration is the four axis scans of Algorithm 5 in its order: row-wise
+// forward (N^{+,0}), column-wise forward (N^{0,+}), row-wise backward
+// (N^{-,0}), column-wise backward (N^{0,-}).  Every step is one elementary
+// update J(p) <- max(J(p), J(q in the scan's neighbour set)) ^ I(p), so the
+// tile never leaves [J ^ I, rho_I(J)].  Halo pixels are sources only.  Four
+// consecutive scans that change nothing (one of each direction, in any
+// phase) mean every pixel already dominates each of its neighbours' offers:
+// the tile is stable, and the sweep stops there.  Returns true if the tile
+// is locally stable; `changed` tells whether any scan changed a pixel.
 template <int CONN>
-__device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters) {
+__device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed) {
   const int l = lane();
   const uint32_t hl = L.J[lidx(l, -1)], hr = L.J[lidx(l, T)];
-  // Stable once four consecutive scans (one of each kind) change nothing:
-  // checked per half iteration, so a quiet backward half followed by a quiet
-  // forward half ends the visit without another full iteration.
-  bool quiet_back = false;
+  int quiet = 0;  // consecutive scans that changed nothing
+  changed = false;
+#define IWPP_SWEEP_SCAN(V, F)                        \
+  {                                                  \
+    uint32_t ch = 0;                                 \
+    scan<CONN, V, F>(L, hl, hr, ch);                 \
+    if (ballot(ch != 0u) != 0u) {                    \
+      quiet = 0;                                     \
+      changed = true;                                \
+    } else if (++quiet == 4) {                       \
+      return true;                                   \
+    }                                                \
+  }
   for (int it = 0; it < max_it; ++it) {
     iters++;
-    uint32_t ch = 0;
-    scan<CONN, false, true>(L, hl, hr, ch);
-    scan<CONN, true, true>(L, hl, hr, ch);
-    const bool quiet_fwd = ballot(ch != 0u) == 0;
-    if (quiet_fwd && quiet_back) return true;
-    ch = 0;
-    scan<CONN, false, false>(L, hl, hr, ch);
-    scan<CONN, true, false>(L, hl, hr, ch);
-    quiet_back = ballot(ch != 0u) == 0;
-    if (quiet_fwd && quiet_back) return true;
+    IWPP_SWEEP_SCAN(false, true)
+    IWPP_SWEEP_SCAN(true, true)
+    IWPP_SWEEP_SCAN(false, false)
+    IWPP_SWEEP_SCAN(true, false)
   }
+#undef IWPP_SWEEP_SCAN
   return false;
 }
 
@@ -477,7 +484,8 @@ __device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
   uint32_t it = 0;
-  const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it);
+  bool changed;
+  const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it, changed);
   iters += it;
   store_tile(tr, L);
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
@@ -506,13 +514,11 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
   uint32_t it = 0;
-  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it);
+  bool changed;
+  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it, changed);
   iters += it;
   visits++;
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
-  // A visit that ends within its first iteration changed nothing; one that
-  // ends later (or is cut off) changed something.
-  const bool changed = it > 1 || !stable;
   if (changed) store_tile(tr, L);
   const uint32_t m = changed ? border_marks<CONN>(L, ot, ob, ol, orr) : 0u;
   mark_reach(s, nx, tr, m, !stable);
