@@ -284,6 +284,15 @@ int32_t iwpp_server_get_stats(iwpp_server* server, iwpp_server_stats* out);
  * context is usable again.  IWPP_EDEVICE if any job failed. */
 int32_t iwpp_server_stop(iwpp_server* server);
 
+/* Timeline of the last persistent kernel of the last call on the context:
+ * us[i] = device time of phase i in microseconds, where phase 0 runs from the
+ * kernel's start to its first grid barrier and phase i from barrier i to
+ * barrier i+1 (reconstruction: phase 0 is the seed pass and phase r round r;
+ * distance transform: phase i is step i+1).  Stamps are taken by one
+ * workgroup on the device's constant-rate clock.  Synchronises with the last
+ * call's stream.  *n = phases written (at most max). */
+int32_t iwpp_round_times(iwpp_ctx* ctx, double* us, int32_t max, int32_t* n);
+
 /* Per-kernel device times recorded since the previous read (needs
  * iwpp_options.profile).  Synchronises with every stream the recorded
  * launches used, writes up to `max` entries in launch order to out[], sets

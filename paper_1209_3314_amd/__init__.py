@@ -171,6 +171,16 @@ class Context:
             self._err(rc)
         return [(_lib.KERNEL_NAMES.get(buf[i].kernel, str(buf[i].kernel)), float(buf[i].ms)) for i in range(n.value)]
 
+    def round_times(self) -> list:
+        """Device time (us) of each phase of the last call's persistent kernel:
+        reconstruction [seed pass, round 1, ...], EDT [step 1, ...]."""
+        buf = (ctypes.c_double * 512)()
+        n = ctypes.c_int32()
+        rc = self._lib.iwpp_round_times(self._h, buf, 512, ctypes.byref(n))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return [float(buf[i]) for i in range(n.value)]
+
     def stats(self) -> dict:
         st = _lib.Stats()
         rc = self._lib.iwpp_get_stats(self._h, ctypes.byref(st))
@@ -241,6 +251,16 @@ class BatchGraph:
         rc = self._lib.iwpp_batch_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream))
         if rc != _lib.IWPP_OK:
             raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
+
+    def round_times(self) -> list:
+        """Device time (us) of each phase of the last call's persistent kernel:
+        reconstruction [seed pass, round 1, ...], EDT [step 1, ...]."""
+        buf = (ctypes.c_double * 512)()
+        n = ctypes.c_int32()
+        rc = self._lib.iwpp_round_times(self._h, buf, 512, ctypes.byref(n))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return [float(buf[i]) for i in range(n.value)]
 
     def stats(self) -> dict:
         st = _lib.Stats()

@@ -17,7 +17,7 @@ IWPP_EBUSY = -4
 EXPORTED = (
     "iwpp_version", "iwpp_create", "iwpp_destroy", "iwpp_last_error",
     "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats", "iwpp_profile_read", "iwpp_run_batch",
-    "iwpp_set_options", "iwpp_server_start", "iwpp_server_submit", "iwpp_server_poll", "iwpp_server_drain",
+    "iwpp_set_options", "iwpp_round_times", "iwpp_server_start", "iwpp_server_submit", "iwpp_server_poll", "iwpp_server_drain",
     "iwpp_server_get_stats", "iwpp_server_stop", "iwpp_batch_graph_create", "iwpp_batch_graph_launch", "iwpp_batch_graph_stats", "iwpp_batch_graph_destroy",
 )
 IWPP_OP_RECON = 1
@@ -130,6 +130,8 @@ def load():
     lib.iwpp_server_get_stats.restype = i32
     lib.iwpp_server_stop.argtypes = [vp]
     lib.iwpp_server_stop.restype = i32
+    lib.iwpp_round_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
+    lib.iwpp_round_times.restype = i32
     lib.iwpp_set_options.argtypes = [vp, ctypes.POINTER(Options)]
     lib.iwpp_set_options.restype = i32
     lib.iwpp_batch_graph_create.argtypes = [vp, ctypes.POINTER(Job), i32, ctypes.POINTER(vp)]

@@ -276,6 +276,7 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.lost = reinterpret_cast<uint32_t*>(fixed + kOffLost);
     a.bar = reinterpret_cast<iwpp::GridBarrier*>(fixed + kOffBarrier);
     a.stats = reinterpret_cast<unsigned long long*>(fixed + kOffStats);
+    a.clock = reinterpret_cast<unsigned long long*>(fixed + kOffClock);
     lr = iwpp::mr_launch(a, g.conn, ctx->opt.persistent_blocks, st, rec, &e);
   } else {
     iwpp::EdtArgs a{};
@@ -294,6 +295,7 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.ovf = reinterpret_cast<uint32_t*>(fixed + kOffOvf);
     a.bar = reinterpret_cast<iwpp::GridBarrier*>(fixed + kOffBarrier);
     a.stats = reinterpret_cast<unsigned long long*>(fixed + kOffStats);
+    a.clock = reinterpret_cast<unsigned long long*>(fixed + kOffClock);
     lr = iwpp::edt_launch(a, g.conn, ctx->opt.persistent_blocks, st, rec, &e);
   }
   if (lr != 0) {
@@ -606,6 +608,31 @@ int32_t iwpp_profile_read(iwpp_ctx* ctx, iwpp_kernel_time* out, int32_t max, int
     out[w].kernel = ks[i];
     out[w].ms = ms[i];
   }
+  *n = w;
+  return IWPP_OK;
+}
+
+int32_t iwpp_round_times(iwpp_ctx* ctx, double* us, int32_t max, int32_t* n) {
+  if (!ctx) return IWPP_EINVAL;
+  if (!us || !n || max < 0) return fail(ctx, IWPP_EINVAL, "round_times: NULL argument");
+  *n = 0;
+  if (!ctx->have_call) return IWPP_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, IWPP_EDEVICE, "round_times: cannot select the context's device");
+  if (hipStreamSynchronize(ctx->last_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, "round_times: the last call's stream reported an error");
+  }
+  unsigned long long h[iwpp::kClockWords];
+  int khz = 0;
+  if (hipMemcpy(h, ctx->fixed + kOffClock, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, "round_times: read failed");
+  }
+  const unsigned long long cnt = h[0] < (unsigned long long)iwpp::kClockWords ? h[0] : iwpp::kClockWords - 1;
+  int32_t w = 0;
+  for (unsigned long long i = 1; i < cnt && w < max; ++i, ++w) us[w] = (double)(h[i + 1] - h[i]) * 1000.0 / khz;
   *n = w;
   return IWPP_OK;
 }

@@ -218,6 +218,18 @@ __device__ __forceinline__ void stage_append(WaveStageT<Item>& s, bool pred, Ite
   s.n += k;
 }
 
+// ---- round timeline -----------------------------------------------------------
+// Workgroup 0 stamps the realtime clock (a constant-rate counter) at kernel
+// start and after every grid barrier: word 0 counts the stamps.  Costs one
+// store per round.
+__device__ __forceinline__ void clock_stamp(unsigned long long* clock, uint32_t& n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n + 1u < 512u) {
+    n++;
+    clock[n] = __builtin_amdgcn_s_memrealtime();
+    clock[0] = n;
+  }
+}
+
 // ---- sharded tile frontier --------------------------------------------------------
 // A round's work list of tiles is split into kShards sub-lists, one per group of
 // workgroups (blockIdx & 7, i.e. one per XCD).  A wave stages its appends in LDS

@@ -337,9 +337,10 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
   WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
   if (threadIdx.x == 0) last_sh = 0u;
-  uint32_t gen = 0;
+  uint32_t gen = 0, nclk = 0;
   unsigned long long changed = 0, visits = 0;
   uint32_t last_round = 0;  // this wave's last round with a change
+  clock_stamp(a.clock, nclk);
   for (uint32_t m = 1;; ++m) {
     // Every workgroup reads the same words: nothing writes them between the
     // previous barrier and this read (step m appends for step m+1).
@@ -384,6 +385,7 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
     }
     shard_flush(s, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
     if (!grid_barrier(a.bar, gen, a.stats)) return;
+    clock_stamp(a.clock, nclk);
   }
   // Both buffers now agree everywhere; write the outputs.
   const uint32_t* fin = a.feat0;

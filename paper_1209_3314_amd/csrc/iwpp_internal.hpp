@@ -43,6 +43,7 @@ struct MrArgs {
   uint32_t* lost;            // [2][64] a listed tile was dropped (capacity), per parity
   GridBarrier* bar;
   unsigned long long* stats;  // [8 shards][16 fields]
+  unsigned long long* clock;  // [kClockWords] round timeline (see kClockWords)
 };
 
 // One distance-transform image of a launch.
@@ -74,11 +75,15 @@ struct EdtArgs {
   uint32_t* ovf;              // never set: a list holds each tile once
   GridBarrier* bar;
   unsigned long long* stats;
+  unsigned long long* clock;  // [kClockWords] round timeline (see kClockWords)
 };
 
 // Bytes of the scratch areas the kernels expect.
 constexpr size_t kBarrierBytes = 4096;
 constexpr size_t kCountsBytes = 3 * 8 * 64 * 4;
+// Round timeline: word 0 = entries written, then realtime-clock stamps (kernel
+// start, then after every grid barrier) of one workgroup.
+constexpr int kClockWords = 512;
 constexpr size_t kLostBytes = 2 * 64 * 4;
 constexpr size_t kStatsBytes = 8 * 16 * 8;
 

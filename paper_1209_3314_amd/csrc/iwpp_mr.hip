@@ -108,13 +108,19 @@ constexpr uint32_t kOutside = 0xFFFFFFF0u;
 // no load may reach past the image).  A chunk cut by the right edge of the
 // image -- one chunk column of the tiles at that edge -- is read byte by byte
 // in a second pass.
+//
+// Seed pass only: with `fresh_top` the halo row above the tile (its 64 bytes,
+// not the corners) is read from the output, where the tile above has already
+// been written by this wave; a value there is a valid lower bound of the
+// result like any other, so it only lets the flood cross the edge earlier.
 template <bool kSeed>
-__device__ void load_region(const TileRef& tr, WaveLds& L) {
+__device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = false) {
   const MrJob& a = tr.j;
   const int y0 = tr.ty * T, x0 = tr.tx * T;
   const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
   const __amdgpu_buffer_rsrc_t rj = make_rsrc(kSeed ? a.marker : a.out, total);
   const __amdgpu_buffer_rsrc_t ri = make_rsrc(a.mask, total);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, total);
   const int rem = a.w - x0;  // image columns from this tile's first column on
   const int cp = (rem < T && (rem & 15) != 0) ? rem >> 4 : -1;  // the cut chunk column, if any
   constexpr int kMain = kRows * 4, kHalo = kRows * 2;
@@ -130,6 +136,14 @@ __device__ void load_region(const TileRef& tr, WaveLds& L) {
     const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)xs : kOutside;
     vj[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rj, off, 0, kSc1));
     vi[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ri, off, 0, kSc1));
+  }
+  v4u vtop = {0u, 0u, 0u, 0u};
+  if (kSeed && fresh_top) {  // wave-uniform; lanes 0..3 hold the row above
+    const int y = y0 - 1, xs = x0 + 16 * (lane() & 3);
+    const bool ok = lane() < 4 && y >= 0 && xs + 16 <= a.w;
+    const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)xs : kOutside;
+    vtop = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ro, off, 0, kSc1));
+    if (lane() < 4) vj[0] = vtop;
   }
 #pragma unroll
   for (int k = 0; k < kPerHalo; ++k) {
@@ -476,10 +490,17 @@ __device__ void mark_reach(WaveStage& s, const Next& nx, const TileRef& tr, uint
 
 // Round-0 visit: the seed pass of one tile (load from the clamped marker,
 // sweep, write back) and its marks for round 1.
+//
+// In strip order (`fresh_top`: the tile above was written by this wave just
+// before) the halo row above comes from the output; `below_next`: the tile
+// below is this wave's next tile and will read this one's result, so it need
+// not be flagged for this tile's bottom edge.
 template <int CONN>
-__device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next& nx, uint32_t t, uint32_t& iters) {
+__device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next& nx, uint32_t t, uint32_t& iters,
+                           bool fresh_top = false, bool below_next = false) {
   const TileRef tr = tile_ref(a, t);
-  load_region<true>(tr, L);
+  if (fresh_top) drain();  // this wave's stores of the tile above are complete
+  load_region<true>(tr, L, fresh_top);
   const int l = lane();
   const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
@@ -489,7 +510,8 @@ __device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   iters += it;
   store_tile(tr, L);
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
-  const uint32_t m = border_marks<CONN>(L, ot, ob, ol, orr);
+  uint32_t m = border_marks<CONN>(L, ot, ob, ol, orr);
+  if (below_next) m &= ~2u;  // bit 1: bottom
   mark_reach(s, nx, tr, m, !stable);
 }
 
@@ -543,14 +565,35 @@ __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
   WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
   const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
   const uint32_t cap = a.list_cap < a.ntiles ? a.list_cap : a.ntiles;
-  uint32_t gen = 0;
+  uint32_t gen = 0, nclk = 0;
   uint32_t visits = 0, iters = 0, seed_iters = 0, rounds = 0, restarts = 0, seeds = 0, first = 0;
+  clock_stamp(a.clock, nclk);
   {
     const Next nx = next_frontier(a, 0u);
-    for (uint32_t t = gw; t < a.ntiles; t += nw) seed_visit<CONN>(a, L, s, nx, t, seed_iters);
+    if (a.njobs == 1u) {
+      // Strip order: each wave seeds vertical strips of S tiles top to bottom,
+      // so the flood crosses the horizontal tile edges inside the seed pass.
+      const MrJob& j = a.job0;
+      const uint32_t tx_n = (uint32_t)j.tiles_x, ty_n = (uint32_t)j.tiles_y;
+      const uint32_t S = (a.ntiles + nw - 1) / nw;
+      const uint32_t sy_n = (ty_n + S - 1) / S, nstrips = tx_n * sy_n;
+      const bool cut = (j.w % T) != 0 && (j.w % T) % 16 != 0;  // right-edge tiles read bytes: stale halo there
+      for (uint32_t sid = gw; sid < nstrips; sid += nw) {
+        const uint32_t tx = sid % tx_n, ty0 = (sid / tx_n) * S;
+        for (uint32_t k = 0; k < S && ty0 + k < ty_n; ++k) {
+          const bool fresh_col = !(cut && tx + 1 == tx_n);
+          const bool fresh = k > 0 && fresh_col;
+          const bool below = fresh_col && k + 1 < S && ty0 + k + 1 < ty_n;  // the next tile reads this one fresh
+          seed_visit<CONN>(a, L, s, nx, (ty0 + k) * tx_n + tx, seed_iters, fresh, below);
+        }
+      }
+    } else {
+      for (uint32_t t = gw; t < a.ntiles; t += nw) seed_visit<CONN>(a, L, s, nx, t, seed_iters);
+    }
     shard_flush(s, nx.list, nx.count, nx.cap, nx.flags, nx.lost);
   }
   bool ok = grid_barrier(a.bar, gen, a.stats);
+  clock_stamp(a.clock, nclk);
   for (uint32_t r = 1; ok; ++r) {
     const uint32_t par = r & 1u;
     // Every workgroup reads the same words: nothing writes them between the
@@ -597,6 +640,7 @@ __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
     if (r == 1) first = visits - before;
     rounds++;
     ok = grid_barrier(a.bar, gen, a.stats);
+    clock_stamp(a.clock, nclk);
   }
   if (lane() == 0) {
     stat_add(a.stats, kStatSeeds, (unsigned long long)first);

@@ -18,7 +18,8 @@ constexpr size_t kOffCounts = kOffBarrier + iwpp::kBarrierBytes;
 constexpr size_t kOffLost = kOffCounts + iwpp::kCountsBytes;
 constexpr size_t kOffOvf = kOffLost + iwpp::kLostBytes;
 constexpr size_t kOffStats = kOffOvf + 256;
-constexpr size_t kFixedBytes = kOffStats + iwpp::kStatsBytes;
+constexpr size_t kOffClock = kOffStats + iwpp::kStatsBytes;  // round timeline of the last group
+constexpr size_t kFixedBytes = kOffClock + iwpp::kClockWords * 8;
 static_assert(kOffStats % 8 == 0, "stats must be 8-byte aligned");
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -96,6 +97,7 @@ void pack_tables(const Plan& plan, uint8_t* host);
 int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* fixed, uint8_t* tables, hipStream_t st,
                      bool first, iwpp::Recorder* rec);
 // Sum the sharded statistics words copied from a fixed area.
+// (The round timeline is read by iwpp_round_times.)
 void fold_stats(const unsigned long long* shards, int op, iwpp_stats* out);
 
 }  // namespace iwpp::rt

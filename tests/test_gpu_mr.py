@@ -128,3 +128,23 @@ def test_whole_slide_tile_16k(env, conn):
     announce("mr 16384^2 conn", conn)
     g, st = run(env, J, I, conn)
     assert np.array_equal(g, oracle.mr_fh(J, I, conn))
+
+
+def test_round_timeline(env):
+    """The per-round timeline of the persistent kernel covers the seed pass and
+    every propagation round, and its phases add up to about the kernel time."""
+    torch, iw, _ = env
+    d = torch.device("cuda", 0)
+    J, I = synth.mr_inputs(700, 900, seed=9, n_disks=20, radius=(5, 20), offset=32)
+    ctx = iw.Context(0, profile=True)
+    try:
+        announce("mr round timeline")
+        ctx.morph_recon(torch.from_numpy(J).to(d), torch.from_numpy(I).to(d), 8)
+        rt = ctx.round_times()
+        st = ctx.stats()
+        ms = dict(ctx.profile_read())["mr_propagate"]
+        assert len(rt) == st["rounds"] + 1
+        assert all(x >= 0 for x in rt)
+        assert 0.5 * ms * 1e3 <= sum(rt) <= 1.1 * ms * 1e3
+    finally:
+        ctx.close()
