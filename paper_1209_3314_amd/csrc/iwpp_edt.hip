@@ -104,9 +104,14 @@ constexpr uint32_t kOutside = 0xFFFFFFF0u;
 constexpr uint32_t kStatePad = 16u;  // readable bytes after the last pixel of a state buffer
 static_assert(kStatePad <= kEdtStatePad, "state buffers must be padded");
 
-// Two region buffers per wave (the rounds of a visit alternate between them).
+// Per-wave LDS: the region, the change masks of two consecutive rounds (one
+// bit per region pixel, a 64-bit word per row) and the active-pixel list.
+constexpr int kMaxActive = (RP - 2) * (RP - 2);  // pixels of round 1
+constexpr int kPerLane = (kMaxActive + kWave - 1) / kWave;
 struct WaveLds {
-  uint32_t F[2][RP * PE];
+  uint32_t F[RP * PE];
+  unsigned long long chg[2][RP];
+  uint16_t list[kMaxActive];
 };
 
 // Load the region of tile tr (rows and columns from K before the tile) from
@@ -155,33 +160,76 @@ __device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
          (t && r ? 64u : 0u) | (b && l ? 128u : 0u) | (b && r ? 256u : 0u);
 }
 
-// K rounds of the operator on the region in LDS, F[0] -> F[1] -> F[0] ...
-// Round i computes region rows and columns [i, RP-i) from round i-1's values;
-// lane l handles column i + (l & 31) of rows i + (l >> 5), + 2, ...  Pixels
-// outside the image stay none.  Accumulates the changed tile pixels (over
-// the rounds), the zone mask (bit 0: a tile pixel changed; bits 1..8: a
-// change in round K within K pixels of that side) and the last round (1..K)
-// with a change.  The result is left in F[K & 1].
+// K rounds of the operator on the region in LDS, in place.  Round i
+// computes region rows and columns [i, RP-i) from round i-1's values: every
+// pixel in round 1, and in later rounds only the pixels with a neighbour (or
+// themselves) changed in round i-1 -- the others cannot change -- gathered
+// into a list from the previous round's change masks.  Each lane computes up
+// to kPerLane list pixels into registers and writes them after the whole
+// wave has read, so every read sees round i-1.  Pixels outside the image stay
+// none.  Accumulates the changed tile pixels (over the rounds), the zone mask
+// (bit 0: a tile pixel changed; bits 1..8: a change in round K within K
+// pixels of that side) and the last round (1..K) with a change.
 template <int CONN>
 __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, uint32_t& zone, uint32_t& last) {
+  static_assert(RP <= 64, "one mask bit per region column");
   const EdtJob& j = tr.j;
   const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
-  const int x = lane() & 31, yb = lane() >> 5;
+  const int l = lane();
 #pragma unroll 1
   for (int i = 1; i <= K; ++i) {
-    const uint32_t* src = L.F[(i - 1) & 1];
-    uint32_t* dst = L.F[i & 1];
-    const int col = i + x;
-    const int qx = rx0 + col;
-    const bool col_act = col < RP - i;
-    const bool col_in = qx >= 0 && qx < j.w;
-    const bool col_tile = col >= K && col < K + TE;
-#pragma unroll 2
-    for (int row = i + yb; row < RP - i; row += 2) {
-      if (!col_act) continue;
-      const int qy = ry0 + row;
+    unsigned long long* now = L.chg[i & 1];
+    const unsigned long long* prev = L.chg[(i - 1) & 1];
+    // The active list of round i (round 1: implicit, every pixel of [1, RP-1)).
+    uint32_t n;
+    if (i == 1) {
+      n = (RP - 2) * (RP - 2);
+    } else {
+      const unsigned long long win = ((1ull << (RP - i)) - 1ull) & ~((1ull << i) - 1ull);  // columns [i, RP-i)
+      unsigned long long m = 0;
+      if (l >= i && l < RP - i) {
+        m = prev[l - 1] | prev[l] | prev[l + 1];
+        m = (m | (m << 1) | (m >> 1)) & win;
+      }
+      // exclusive prefix of the per-row counts over the lanes
+      const uint32_t c = (uint32_t)__popcll(m);
+      uint32_t incl = c;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o);
+        if (l >= o) incl += v;
+      }
+      n = (uint32_t)readlane(incl, kWave - 1);
+      uint32_t at = incl - c;
+      while (m) {
+        const int col = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        L.list[at++] = (uint16_t)((l << 8) | col);
+      }
+    }
+    if (l < RP) now[l] = 0ull;
+    wave_sync();
+    // Compute (reads only).
+    uint32_t res[kPerLane];
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k) {
+      res[k] = kNone;
+      const uint32_t idx = (uint32_t)(k * kWave + l);
+      if ((uint32_t)(k * kWave) >= n) continue;  // wave-uniform
+      if (idx >= n) continue;
+      int row, col;
+      if (i == 1) {
+        row = 1 + (int)(idx / (RP - 2));
+        col = 1 + (int)(idx - (uint32_t)(row - 1) * (RP - 2));
+      } else {
+        const uint32_t e = L.list[idx];
+        row = (int)(e >> 8);
+        col = (int)(e & 0xffu);
+      }
+      const int qy = ry0 + row, qx = rx0 + col;
+      if (qy < 0 || qy >= j.h || qx < 0 || qx >= j.w) continue;  // outside the image: stays none
       const uint32_t q = pack_yx(qy, qx);
-      const uint32_t* c = &src[row * PE + col];
+      const uint32_t* c = &L.F[row * PE + col];
       const uint32_t old = c[0];
       unsigned long long best = ((unsigned long long)d2(q, old) << 32) | old;
       offer(q, c[-PE], best);
@@ -194,10 +242,30 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
         offer(q, c[PE - 1], best);
         offer(q, c[PE + 1], best);
       }
-      const bool inside = col_in && qy >= 0 && qy < j.h;
-      const uint32_t nv = inside ? (uint32_t)best : kNone;
-      dst[row * PE + col] = nv;
-      if (inside && col_tile && row >= K && row < K + TE && nv != old) {
+      res[k] = (uint32_t)best;
+    }
+    wave_sync();
+    // Write back, recording the changes.
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k) {
+      const uint32_t idx = (uint32_t)(k * kWave + l);
+      if ((uint32_t)(k * kWave) >= n) continue;
+      if (idx >= n) continue;
+      int row, col;
+      if (i == 1) {
+        row = 1 + (int)(idx / (RP - 2));
+        col = 1 + (int)(idx - (uint32_t)(row - 1) * (RP - 2));
+      } else {
+        const uint32_t e = L.list[idx];
+        row = (int)(e >> 8);
+        col = (int)(e & 0xffu);
+      }
+      uint32_t* c = &L.F[row * PE + col];
+      const uint32_t old = c[0];
+      if (res[k] == old) continue;
+      *c = res[k];
+      atomicOr(&now[row], 1ull << col);
+      if (row >= K && row < K + TE && col >= K && col < K + TE) {
         changed++;
         last = (uint32_t)i;
         zone |= 1u;
@@ -367,7 +435,7 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
       const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
       if (lane() == 0) cstore(flg + t, 0u);
       const TileRef tr = tile_ref(a, t);
-      load_region(rd, tr, L.F[0]);
+      load_region(rd, tr, L.F);
       uint32_t c = 0, zone = 0, lr = 0;
       relax_steps<CONN>(L, tr, c, zone, lr);
       changed += c;
@@ -379,7 +447,7 @@ __global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
       uint32_t lw = lr;
       for (int o = 32; o > 0; o >>= 1) lw = umax32(lw, (uint32_t)__shfl_xor((int)lw, o));
       if (lw) last_round = umax32(last_round, (m - 1u) * (uint32_t)K + lw);
-      store_tile(L.F[K & 1], wr, tr);
+      store_tile(L.F, wr, tr);
       mark_reach(a, s, nx, tr, z);
       wave_sync();  // LDS is reloaded by the next visit
     }
