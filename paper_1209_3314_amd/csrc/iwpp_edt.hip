@@ -395,7 +395,7 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
 }
 
 template <int CONN>
-__global__ __launch_bounds__(256) void k_rounds(EdtArgs a) {
+__global__ __launch_bounds__(256, 4) void k_rounds(EdtArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
   __shared__ uint32_t cnt[kShards];
