@@ -295,30 +295,30 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint3
 // the tile is stable, and the sweep stops there.  Returns true if the tile
 // is locally stable; `changed` tells whether any scan changed a pixel.
 template <int CONN>
-__device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed) {
+__device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed, int start = 0) {
   const int l = lane();
   const uint32_t hl = L.J[lidx(l, -1)], hr = L.J[lidx(l, T)];
   int quiet = 0;  // consecutive scans that changed nothing
   changed = false;
-#define IWPP_SWEEP_SCAN(V, F)                        \
-  {                                                  \
-    uint32_t ch = 0;                                 \
-    scan<CONN, V, F>(L, hl, hr, ch);                 \
-    if (ballot(ch != 0u) != 0u) {                    \
-      quiet = 0;                                     \
-      changed = true;                                \
-    } else if (++quiet == 4) {                       \
-      return true;                                   \
-    }                                                \
+  // `start` picks the first scan (0 rows forward, 1 columns forward, 2 rows
+  // backward, 3 columns backward), e.g. the one that carries a raised halo
+  // side into the tile; the cyclic order is Algorithm 5's.
+  for (int n = 0; n < 4 * max_it; ++n) {
+    if ((n & 3) == 0) iters++;
+    uint32_t ch = 0;
+    switch ((start + n) & 3) {
+      case 0: scan<CONN, false, true>(L, hl, hr, ch); break;
+      case 1: scan<CONN, true, true>(L, hl, hr, ch); break;
+      case 2: scan<CONN, false, false>(L, hl, hr, ch); break;
+      default: scan<CONN, true, false>(L, hl, hr, ch); break;
+    }
+    if (ballot(ch != 0u) != 0u) {
+      quiet = 0;
+      changed = true;
+    } else if (++quiet == 4) {
+      return true;
+    }
   }
-  for (int it = 0; it < max_it; ++it) {
-    iters++;
-    IWPP_SWEEP_SCAN(false, true)
-    IWPP_SWEEP_SCAN(true, true)
-    IWPP_SWEEP_SCAN(false, false)
-    IWPP_SWEEP_SCAN(true, false)
-  }
-#undef IWPP_SWEEP_SCAN
   return false;
 }
 
@@ -367,15 +367,15 @@ __device__ uint32_t border_marks(const WaveLds& L, uint32_t ot, uint32_t ob, uin
   return m;
 }
 
-// Can a halo pixel raise a border pixel of the tile?  (Algorithm 5's
-// propagation condition read from the receiving side: J(p) < J(h) and
+// Which sides' halo pixels can raise a border pixel of the tile?  (Algorithm
+// 5's propagation condition read from the receiving side: J(p) < J(h) and
 // J(p) < I(p), for p on the border and h a halo neighbour of p.)  A tile that
 // was locally stable after its last visit can only have become raisable this
-// way, because only its halo changed since.  Wave-uniform.
+// way, because only its halo changed since.  Wave-uniform bit mask.
 template <int CONN>
-__device__ bool border_raisable(const WaveLds& L) {
+__device__ uint32_t border_raisable(const WaveLds& L) {
   const int l = lane();
-  bool r = false;
+  bool rt = false, rb = false, rl = false, rr = false;
   // p on row 0 (halo row -1), row T-1 (halo row T), column 0 (halo column -1), column T-1 (halo column T)
   const uint32_t pt = L.J[lidx(0, l)], it = L.I[lidx(0, l)];
   const uint32_t pb = L.J[lidx(T - 1, l)], ib = L.I[lidx(T - 1, l)];
@@ -385,12 +385,13 @@ __device__ bool border_raisable(const WaveLds& L) {
   for (int d = -1; d <= 1; ++d) {
     if (CONN == 4 && d != 0) continue;
     const int c = l + d;  // -1 .. 64: halo corners included
-    r |= pt < umin(L.J[lidx(-1, c)], it);
-    r |= pb < umin(L.J[lidx(T, c)], ib);
-    r |= pl < umin(L.J[lidx(c, -1)], il);
-    r |= pr < umin(L.J[lidx(c, T)], ir);
+    rt |= pt < umin(L.J[lidx(-1, c)], it);
+    rb |= pb < umin(L.J[lidx(T, c)], ib);
+    rl |= pl < umin(L.J[lidx(c, -1)], il);
+    rr |= pr < umin(L.J[lidx(c, T)], ir);
   }
-  return ballot(r) != 0u;
+  // bits: 0 top, 1 bottom, 2 left, 3 right
+  return (ballot(rt) ? 1u : 0u) | (ballot(rb) ? 2u : 0u) | (ballot(rl) ? 4u : 0u) | (ballot(rr) ? 8u : 0u);
 }
 
 // ---- raisable-pixel test (full rounds of the bounded mode) -------------------------
@@ -526,18 +527,23 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
                            uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
   const TileRef tr = tile_ref(a, t);
   load_region<false>(tr, L);
+  int start = 0;
   if (check) {
     if (!lds_dirty<CONN>(L, seeds)) return;
   } else {
     const bool was_unsettled = readlane(lane() == 0 ? cload(a.unsettled + t) : 0u, 0) != 0u;
-    if (!was_unsettled && !border_raisable<CONN>(L)) return;
+    const uint32_t sides = border_raisable<CONN>(L);
+    if (!was_unsettled && sides == 0u) return;
+    // First scan: the one moving away from a raisable side (top: columns
+    // forward, bottom: columns backward, left: rows forward, right: rows backward).
+    start = (sides & 1u) ? 1 : (sides & 2u) ? 3 : (sides & 4u) ? 0 : (sides & 8u) ? 2 : 0;
   }
   const int l = lane();
   const uint32_t ot = L.J[lidx(0, l)], ob = L.J[lidx(T - 1, l)];
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
   uint32_t it = 0;
   bool changed;
-  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it, changed);
+  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it, changed, start);
   iters += it;
   visits++;
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
