@@ -62,7 +62,8 @@ typedef struct {
    * seed detection, as the paper re-runs propagation from its partial output
    * after its global queue overflows (Sec. 3.2, Sec. 5.2.4).  0 = no limit. */
   int64_t mr_list_capacity;
-  /* Cap on sweep iterations per tile visit before the tile is re-queued. */
+  /* Cap on sweep iterations per tile visit before the tile is re-queued
+   * (0 = 2). */
   int32_t mr_max_sweeps;
   /* Workgroups of the persistent kernels (0 = fill the device). */
   int32_t persistent_blocks;
@@ -72,7 +73,7 @@ typedef struct {
   int32_t profile;
   /* Cap on sweep iterations per tile in the reconstruction seed pass (the
    * number of raster/anti-raster scan pairs before the queue takes over; the
-   * paper varies the number of initial scans in Table 1). */
+   * paper varies the number of initial scans in Table 1; 0 = 2). */
   int32_t mr_seed_sweeps;
   int32_t reserved[6];
 } iwpp_options;
