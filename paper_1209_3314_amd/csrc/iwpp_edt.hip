@@ -55,7 +55,7 @@ constexpr int kStageCap = 32;
 constexpr uint32_t kNone = 0x80008000u;
 constexpr uint32_t kMaxSteps = (1u << 20) / K;
 static_assert(RP - 2 <= 32, "a round's region row must fit 32 lanes");
-static_assert(K % 4 == 0 || K < 4, "region chunks must not straddle the image's left edge");
+static_assert(K % 4 == 0, "region chunks must not straddle the image's left edge");
 static_assert(K <= TE, "a change must reach no farther than the neighbouring tiles");
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));

@@ -10,7 +10,7 @@ struct GridBarrier;
 
 // Tile geometry shared by the host plans and the kernels.
 constexpr int kMrTile = 64;   // reconstruction tiles: 64 x 64 pixels
-constexpr int kEdtHalo = 4;   // EDT rounds per tile visit (= halo width)
+constexpr int kEdtHalo = 4;   // EDT rounds per tile visit (= halo width; 8 measured slower)
 constexpr int kEdtTile = 26;  // EDT tiles: 26 x 26 pixels (a 34 x 34 region with the halo)
 constexpr size_t kEdtStatePad = 256;  // bytes after each EDT state buffer (16-byte loads may cross the end)
 
