@@ -108,8 +108,9 @@ size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
   const int ts = op == IWPP_OP_RECON ? iwpp::kMrTile : iwpp::kEdtTile;
   const uint64_t t = (uint64_t)((h + ts - 1) / ts) * (uint64_t)((w + ts - 1) / ts);
   const uint64_t np = (uint64_t)h * (uint64_t)w;
-  // 5 tile words (+ alignment slack of the per-group arrays is added by the caller)
-  return (size_t)(80 * t + 20 * 256 + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad : 0) +
+  // 5 tile words, and for recon a 256-byte border-column block per tile (+
+  // alignment slack of the per-group arrays is added by the caller)
+  return (size_t)(80 * t + 20 * 256 + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad : 256 * t) +
                   (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
 }
 
@@ -212,7 +213,9 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
         }
       }
       if (g.njobs() == 0) continue;
-      if (g.ntiles >= 0x7FFFFFFFull) return fail(ctx, IWPP_EINVAL, std::string(who) + ": too many tiles in one group");
+      // recon addresses its 256-byte border-column blocks with 32-bit offsets
+      if (g.ntiles >= (op == IWPP_OP_RECON ? (1ull << 24) : 0x7FFFFFFFull))
+        return fail(ctx, IWPP_EINVAL, std::string(who) + ": too many tiles in one group");
       g.table_off = plan.table_bytes;
       plan.table_bytes += g.table_bytes();
       if (g.scratch_bytes() > plan.scratch_bytes) plan.scratch_bytes = g.scratch_bytes();
@@ -274,6 +277,7 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * tb);
     a.unsettled = reinterpret_cast<uint32_t*>(scratch + 18 * tb);
     a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 19 * tb) : nullptr;
+    a.cols = scratch + 20 * tb;
     a.jobs = nj > 1 ? reinterpret_cast<const iwpp::MrJob*>(tables + g.table_off) : nullptr;
     a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
     a.lost = reinterpret_cast<uint32_t*>(fixed + kOffLost);

@@ -39,6 +39,7 @@ struct MrArgs {
   uint32_t* flags;           // [2][ntiles] tile on the round's list, per round parity
   uint32_t* lists;           // [2][8 shards][ntiles] tile lists per round parity
   uint32_t* unsettled;       // [ntiles] the tile's last visit stopped at the sweep cap
+  uint8_t* cols;             // [ntiles][4][64] each tile's border columns: J left, J right, I left, I right
   uint32_t* counts;          // [3 round slots][8 shards][64] list fill levels (256 B apart)
   uint32_t* lost;            // [2][64] a listed tile was dropped (capacity), per parity
   GridBarrier* bar;

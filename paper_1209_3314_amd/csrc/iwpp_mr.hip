@@ -113,8 +113,14 @@ constexpr uint32_t kOutside = 0xFFFFFFF0u;
 // not the corners) is read from the output, where the tile above has already
 // been written by this wave; a value there is a valid lower bound of the
 // result like any other, so it only lets the flood cross the edge earlier.
+//
+// Propagation rounds (not the seed pass) read the halo columns and corners
+// from the neighbouring tiles' border-column blocks (`cols`, `cols_bytes`
+// long, rewritten whenever a tile is written): one byte per lane from four
+// 64-byte runs instead of 132 words from 66 image rows.
 template <bool kSeed>
-__device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = false) {
+__device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = false, const uint8_t* cols = nullptr,
+                            uint32_t cols_bytes = 0, uint32_t t = 0) {
   const MrJob& a = tr.j;
   const int y0 = tr.ty * T, x0 = tr.tx * T;
   const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
@@ -145,15 +151,38 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
     vtop = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ro, off, 0, kSc1));
     if (lane() < 4) vj[0] = vtop;
   }
+  if (kSeed) {
 #pragma unroll
-  for (int k = 0; k < kPerHalo; ++k) {
-    const int idx = lane() + k * kWave;
-    const int y = y0 - 1 + (idx >> 1);
-    const int x = (idx & 1) ? x0 + T : x0 - 1;
-    const bool ok = idx < kHalo && y >= 0 && y < a.h && x >= 3 && x < a.w;
-    const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)(x - 3) : kOutside;
-    hj[k] = __builtin_amdgcn_raw_buffer_load_b32(rj, off, 0, kSc1);
-    hi[k] = __builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, kSc1);
+    for (int k = 0; k < kPerHalo; ++k) {
+      const int idx = lane() + k * kWave;
+      const int y = y0 - 1 + (idx >> 1);
+      const int x = (idx & 1) ? x0 + T : x0 - 1;
+      const bool ok = idx < kHalo && y >= 0 && y < a.h && x >= 3 && x < a.w;
+      const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)(x - 3) : kOutside;
+      hj[k] = __builtin_amdgcn_raw_buffer_load_b32(rj, off, 0, kSc1);
+      hi[k] = __builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, kSc1);
+    }
+  } else {
+    // Lane l: row l of the left neighbour's right column and of the right
+    // neighbour's left column (J and I); lanes 0..3 also one corner each:
+    // top-left, top-right, bottom-left, bottom-right.
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(cols, cols_bytes);
+    const int l = lane();
+    const int tx_n = tr.j.tiles_x, ty_n = tr.j.tiles_y;
+    const bool has_l = tr.tx > 0, has_r = tr.tx + 1 < tx_n;
+    const uint32_t bl = (t - 1u) * 256u, br = (t + 1u) * 256u;
+    const uint32_t ol = has_l ? bl + 64u + (uint32_t)l : kOutside, or_ = has_r ? br + (uint32_t)l : kOutside;
+    hj[0] = __builtin_amdgcn_raw_buffer_load_b8(rc, ol, 0, kSc1);
+    hi[0] = __builtin_amdgcn_raw_buffer_load_b8(rc, ol == kOutside ? kOutside : ol + 128u, 0, kSc1);
+    hj[1] = __builtin_amdgcn_raw_buffer_load_b8(rc, or_, 0, kSc1);
+    hi[1] = __builtin_amdgcn_raw_buffer_load_b8(rc, or_ == kOutside ? kOutside : or_ + 128u, 0, kSc1);
+    const int cdy = (l & 2) ? 1 : -1, cdx = (l & 1) ? 1 : -1;
+    const bool has_c = l < 4 && tr.ty + cdy >= 0 && tr.ty + cdy < ty_n && tr.tx + cdx >= 0 && tr.tx + cdx < tx_n;
+    // the corner pixel is the diagonal tile's (right column if it lies left) row 63 (if above) or 0
+    const uint32_t tc = (uint32_t)((int)t + cdy * tx_n + cdx);
+    const uint32_t oc = has_c ? tc * 256u + (cdx < 0 ? 64u : 0u) + (cdy < 0 ? 63u : 0u) : kOutside;
+    hj[2] = __builtin_amdgcn_raw_buffer_load_b8(rc, oc, 0, kSc1);
+    hi[2] = __builtin_amdgcn_raw_buffer_load_b8(rc, oc == kOutside ? kOutside : oc + 128u, 0, kSc1);
   }
 #pragma unroll
   for (int k = 0; k < kPerMain; ++k) {
@@ -168,15 +197,28 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
       di[d] = vi[k][d];
     }
   }
+  if (kSeed) {
 #pragma unroll
-  for (int k = 0; k < kPerHalo; ++k) {
-    const int idx = lane() + k * kWave;
-    if (idx >= kHalo) continue;
-    const int ry = idx >> 1;
-    const uint32_t jb = hj[k] >> 24, ib = hi[k] >> 24;
-    const int at = lidx(ry - 1, (idx & 1) ? T : -1);
-    L.J[at] = (uint8_t)(kSeed ? umin(jb, ib) : jb);
-    L.I[at] = (uint8_t)ib;
+    for (int k = 0; k < kPerHalo; ++k) {
+      const int idx = lane() + k * kWave;
+      if (idx >= kHalo) continue;
+      const int ry = idx >> 1;
+      const uint32_t jb = hj[k] >> 24, ib = hi[k] >> 24;
+      const int at = lidx(ry - 1, (idx & 1) ? T : -1);
+      L.J[at] = (uint8_t)umin(jb, ib);
+      L.I[at] = (uint8_t)ib;
+    }
+  } else {
+    const int l = lane();
+    L.J[lidx(l, -1)] = (uint8_t)hj[0];
+    L.I[lidx(l, -1)] = (uint8_t)hi[0];
+    L.J[lidx(l, T)] = (uint8_t)hj[1];
+    L.I[lidx(l, T)] = (uint8_t)hi[1];
+    if (l < 4) {
+      const int at = lidx((l & 2) ? T : -1, (l & 1) ? T : -1);
+      L.J[at] = (uint8_t)hj[2];
+      L.I[at] = (uint8_t)hi[2];
+    }
   }
   if (cp >= 0) {  // wave-uniform: only tiles cut by the right edge of the image
     const int nb = rem - 16 * cp, xs = x0 + 16 * cp;
@@ -228,6 +270,19 @@ __device__ void store_tile(const TileRef& tr, const WaveLds& L) {
         if (b < nb)
           __builtin_amdgcn_raw_buffer_store_b8((unsigned char)(v[b >> 2] >> (8 * (b & 3))), ro, off + b, 0, kSc1);
     }
+  }
+}
+
+// Write the tile's border columns (J, and with `mask` also I) into its block
+// of `cols`: [J left | J right | I left | I right], 64 bytes each.
+__device__ void store_cols(const MrArgs& a, uint32_t t, const WaveLds& L, bool mask) {
+  const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.cols + (size_t)t * 256u, 256u);
+  const int l = lane();
+  __builtin_amdgcn_raw_buffer_store_b8(L.J[lidx(l, 0)], rc, (uint32_t)l, 0, kSc1);
+  __builtin_amdgcn_raw_buffer_store_b8(L.J[lidx(l, T - 1)], rc, 64u + (uint32_t)l, 0, kSc1);
+  if (mask) {
+    __builtin_amdgcn_raw_buffer_store_b8(L.I[lidx(l, 0)], rc, 128u + (uint32_t)l, 0, kSc1);
+    __builtin_amdgcn_raw_buffer_store_b8(L.I[lidx(l, T - 1)], rc, 192u + (uint32_t)l, 0, kSc1);
   }
 }
 
@@ -510,6 +565,7 @@ __device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it, changed);
   iters += it;
   store_tile(tr, L);
+  store_cols(a, t, L, true);
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
   uint32_t m = border_marks<CONN>(L, ot, ob, ol, orr);
   if (below_next) m &= ~2u;  // bit 1: bottom
@@ -526,7 +582,7 @@ template <int CONN>
 __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next& nx, uint32_t t, bool check,
                            uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
   const TileRef tr = tile_ref(a, t);
-  load_region<false>(tr, L);
+  load_region<false>(tr, L, false, a.cols, a.ntiles * 256u, t);
   int start = 0;
   if (check) {
     if (!lds_dirty<CONN>(L, seeds)) return;
@@ -547,7 +603,10 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   iters += it;
   visits++;
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
-  if (changed) store_tile(tr, L);
+  if (changed) {
+    store_tile(tr, L);
+    store_cols(a, t, L, false);
+  }
   const uint32_t m = changed ? border_marks<CONN>(L, ot, ob, ol, orr) : 0u;
   mark_reach(s, nx, tr, m, !stable);
 }
