@@ -68,6 +68,28 @@ __device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t fill) {
 __device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t fill) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
 }
+// lane i receives v from lane i-1 (i+1); lane 0 (63) receives 0, the identity
+// of an unsigned max, so a max of the result folds into one DPP instruction.
+__device__ __forceinline__ uint32_t from_left0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t from_right0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+}
+// A value the wave holds in common, moved to scalar registers word by word
+// (e.g. a job descriptor read through a per-tile table), so that buffer
+// resources built from it need no per-lane loop.
+template <class V>
+__device__ __forceinline__ V uniform(const V& v) {
+  static_assert(sizeof(V) % 4 == 0, "whole words");
+  uint32_t w[sizeof(V) / 4];
+  __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(V) / 4); ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)w[i]);
+  V r;
+  __builtin_memcpy(&r, w, sizeof(V));
+  return r;
+}
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }

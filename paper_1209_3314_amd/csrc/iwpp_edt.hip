@@ -84,7 +84,7 @@ struct TileRef {
 
 __device__ __forceinline__ TileRef tile_ref(const EdtArgs& a, uint32_t t) {
   TileRef r;
-  r.j = a.njobs == 1u ? a.job0 : a.jobs[a.tile_job[t]];
+  r.j = uniform(a.njobs == 1u ? a.job0 : a.jobs[a.tile_job[t]]);
   const uint32_t lt = t - r.j.tile_base;
   r.ty = (int)(lt / (uint32_t)r.j.tiles_x);
   r.tx = (int)(lt - (uint32_t)r.ty * (uint32_t)r.j.tiles_x);

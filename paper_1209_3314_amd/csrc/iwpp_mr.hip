@@ -56,6 +56,9 @@ constexpr int kStageCap = 128;
 constexpr uint32_t kMaxRounds = 1u << 20;
 
 __device__ __forceinline__ int lidx(int y, int x) { return (y + 1) * P + x + kOff; }  // y, x in [-1, 64]
+// Column 65 of rows -1..64 is never written by a tile load: it is cleared once
+// per kernel and read as zeros (it shares bytes with no other column).
+constexpr int kZeroCol = T + 1;
 
 struct WaveLds {
   uint8_t J[kRegion];
@@ -86,7 +89,7 @@ struct TileRef {
 
 __device__ __forceinline__ TileRef tile_ref(const MrArgs& a, uint32_t t) {
   TileRef r;
-  r.j = a.njobs == 1u ? a.job0 : a.jobs[a.tile_job[t]];
+  r.j = uniform(a.njobs == 1u ? a.job0 : a.jobs[a.tile_job[t]]);
   const uint32_t lt = t - r.j.tile_base;
   r.ty = (int)(lt / (uint32_t)r.j.tiles_x);
   r.tx = (int)(lt - (uint32_t)r.ty * (uint32_t)r.j.tiles_x);
@@ -304,8 +307,10 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint3
     prev = kForward ? hl : hr;
   // Vertical 8-connected scans: lane 0's left neighbour and lane 63's right
   // neighbour in the previous row are halo pixels; one LDS read per step
-  // (lane 0 reads column -1, every other lane column 64) supplies both.
-  const int halo_col = l == 0 ? -1 : T;
+  // supplies both (lane 0 reads column -1, lane 63 column 64, the others
+  // column 65, which holds zeros), and the in-tile diagonal neighbours come
+  // from the adjacent lanes with the max folded into the lane shift.
+  const int halo_col = l == 0 ? -1 : (l == T - 1 ? T : kZeroCol);
 #pragma unroll 1
   for (int c = 0; c < T / kChunk; ++c) {
     uint32_t vj[kChunk], vi[kChunk], vf[kChunk];
@@ -319,9 +324,14 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint3
     }
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
-      uint32_t m = umax(vj[k], prev);
-      if (kVertical && CONN == 8) m = umax(m, umax(from_left(prev, vf[k]), from_right(prev, vf[k])));
-      const uint32_t nv = umin(m, vi[k]);
+      uint32_t nv;
+      if (kVertical && CONN == 8) {
+        // J <= I throughout, so min(max(J, offers), I) needs no median
+        const uint32_t m = umax(from_right0(prev), umax(from_left0(prev), umax(umax(vj[k], prev), vf[k])));
+        nv = umin(m, vi[k]);
+      } else {
+        nv = umin(umax(vj[k], prev), vi[k]);
+      }
       // Values only rise (J <= I holds throughout), so the sum of increases
       // is nonzero iff something changed; a sum keeps the compiler from
       // deferring per-step comparisons and holding old values live.
@@ -339,6 +349,53 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint3
   wave_sync();
 }
 
+// Is the tile in LDS locally stable, i.e. no tile pixel q with J(q) < I(q)
+// has a neighbour p (tile or halo) with J(p) > J(q)?  That is the condition
+// four quiet scans establish, tested in one top-to-bottom walk with lane =
+// column.  h(y) is the largest horizontal neighbour of row y (the halo
+// columns enter through column 65's zeros, as in the scans) and s(y) =
+// max(h(y), J(y)); q in row y sees max(h(y), J(y-1), J(y+1)) with
+// 4-connectivity and max(h(y), s(y-1), s(y+1)) with 8-connectivity.
+template <int CONN>
+__device__ bool lds_settled(const WaveLds& L) {
+  const int l = lane();
+  const int hc = l == 0 ? -1 : (l == T - 1 ? T : kZeroCol);
+  auto hnb = [&](uint32_t j, int y) {
+    return umax(umax(from_left0(j), from_right0(j)), (uint32_t)L.J[lidx(y, hc)]);
+  };
+  uint32_t jp = L.J[lidx(-1, l)];
+  uint32_t sp = CONN == 8 ? umax(hnb(jp, -1), jp) : jp;  // s(y-1) (J(y-1) for 4-conn)
+  uint32_t jc = L.J[lidx(0, l)], ic = L.I[lidx(0, l)];
+  uint32_t hcur = hnb(jc, 0);
+#pragma unroll 1
+  for (int c = 0; c < T / kChunk; ++c) {
+    uint32_t nj[kChunk], ni[kChunk], nf[kChunk];
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int y = c * kChunk + k + 1;  // row below the one tested
+      nj[k] = L.J[lidx(y, l)];
+      ni[k] = y < T ? L.I[lidx(y, l)] : 0u;
+      nf[k] = L.J[lidx(y, hc)];
+    }
+    bool raisable = false;
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const uint32_t jn = nj[k];
+      const uint32_t hn = umax(umax(from_left0(jn), from_right0(jn)), nf[k]);
+      const uint32_t sn = CONN == 8 ? umax(hn, jn) : jn;
+      const uint32_t m = umax(umax(sp, sn), hcur);
+      raisable |= jc < umin(m, ic);
+      sp = CONN == 8 ? umax(hcur, jc) : jc;
+      jc = jn;
+      ic = ni[k];
+      hcur = hn;
+    }
+    if (ballot(raisable) != 0u) return false;
+    asm volatile("" ::: "memory");
+  }
+  return true;
+}
+
 // Sweep the tile in LDS until it is locally stable, or `max_it` iterations.
 // One iteration is the four axis scans of Algorithm 5 in its order: row-wise
 // forward (N^{+,0}), column-wise forward (N^{0,+}), row-wise backward
@@ -347,8 +404,12 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint3
 // tile never leaves [J ^ I, rho_I(J)].  Halo pixels are sources only.  Four
 // consecutive scans that change nothing (one of each direction, in any
 // phase) mean every pixel already dominates each of its neighbours' offers:
-// the tile is stable, and the sweep stops there.  Returns true if the tile
-// is locally stable; `changed` tells whether any scan changed a pixel.
+// the tile is stable.  The same holds when the one-pass test `lds_settled`
+// finds no raisable pixel.  With 8-connectivity the test runs after every
+// scan that changed nothing, which usually ends the sweep one scan after the
+// last change instead of four; with 4-connectivity a scan costs about half
+// as much as the test, which then does not pay.  Returns true if the tile is
+// locally stable; `changed` tells whether any scan changed a pixel.
 template <int CONN>
 __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed, int start = 0) {
   const int l = lane();
@@ -370,7 +431,7 @@ __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& change
     if (ballot(ch != 0u) != 0u) {
       quiet = 0;
       changed = true;
-    } else if (++quiet == 4) {
+    } else if (++quiet == 4 || (CONN == 8 && lds_settled<CONN>(L))) {
       return true;
     }
   }
@@ -628,6 +689,8 @@ __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
   WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
+  L.J[lidx(lane() - 1, kZeroCol)] = 0;  // rows -1..62
+  if (lane() < 2) L.J[lidx(T - 1 + lane(), kZeroCol)] = 0;  // rows 63, 64
   const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
   const uint32_t cap = a.list_cap < a.ntiles ? a.list_cap : a.ntiles;
   uint32_t gen = 0, nclk = 0;
