@@ -289,45 +289,69 @@ __device__ void store_cols(const MrArgs& a, uint32_t t, const WaveLds& L, bool m
   }
 }
 
-// One axis scan of the tile in LDS.  Vertical scans walk the rows with lane =
-// column, using the previous row's values of the three (8-conn) or one
-// (4-conn) upper/lower neighbours; horizontal scans walk the columns with
-// lane = row, using the previous column.  Steps are loaded from LDS in chunks
-// of kChunk so the wave pays one LDS latency per chunk rather than per step;
-// results are written back unconditionally and increases accumulate in `ch`.
+// Apply every halo pixel's offer to the border pixels it touches, once:
+// J(p) <- max(J(p), min(J(h), I(p))) for border pixel p and halo neighbour h.
+// Halo pixels do not change during a visit and J only rises, so afterwards no
+// halo offer can raise anything again and the scans can ignore the halo (it
+// acts as zeros there).  Rows first, then columns, so a corner pixel takes
+// both.  Returns (wave-uniform) whether a pixel rose.
+template <int CONN>
+__device__ bool fold_halo(WaveLds& L) {
+  const int l = lane();
+  bool up = false;
+  auto offer = [&](int hy0, int hx0, int hy1, int hx1, int hy2, int hx2) {  // max of the halo neighbours
+    uint32_t h = L.J[lidx(hy1, hx1)];
+    if (CONN == 8) h = umax(h, umax((uint32_t)L.J[lidx(hy0, hx0)], (uint32_t)L.J[lidx(hy2, hx2)]));
+    return h;
+  };
+  const uint32_t ht = offer(-1, l - 1, -1, l, -1, l + 1), hb = offer(T, l - 1, T, l, T, l + 1);
+  const uint32_t jt = L.J[lidx(0, l)], it = L.I[lidx(0, l)], jb = L.J[lidx(T - 1, l)], ib = L.I[lidx(T - 1, l)];
+  const uint32_t nt = umax(jt, umin(ht, it)), nb = umax(jb, umin(hb, ib));
+  L.J[lidx(0, l)] = (uint8_t)nt;
+  L.J[lidx(T - 1, l)] = (uint8_t)nb;
+  up |= nt != jt || nb != jb;
+  const uint32_t hl = offer(l - 1, -1, l, -1, l + 1, -1), hr = offer(l - 1, T, l, T, l + 1, T);
+  const uint32_t jl = L.J[lidx(l, 0)], il = L.I[lidx(l, 0)], jr = L.J[lidx(l, T - 1)], ir = L.I[lidx(l, T - 1)];
+  const uint32_t nl = umax(jl, umin(hl, il)), nr = umax(jr, umin(hr, ir));
+  L.J[lidx(l, 0)] = (uint8_t)nl;
+  L.J[lidx(l, T - 1)] = (uint8_t)nr;
+  up |= nl != jl || nr != jr;
+  wave_sync();
+  return ballot(up) != 0u;
+}
+
+// One axis scan of the tile in LDS, after `fold_halo`: the halo is ignored.
+// Vertical scans walk the rows with lane = column, using the previous row's
+// values of the three (8-conn) or one (4-conn) upper/lower neighbours;
+// horizontal scans walk the columns with lane = row, using the previous
+// column.  Steps are loaded from LDS in chunks of kChunk so the wave pays one
+// LDS latency per chunk rather than per step; results are written back
+// unconditionally and increases accumulate in `ch`.
 constexpr int kChunk = 16;
 
 template <int CONN, bool kVertical, bool kForward>
-__device__ __forceinline__ void scan(WaveLds& L, uint32_t hl, uint32_t hr, uint32_t& ch) {
+__device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
   const int l = lane();
-  uint32_t prev;
-  if (kVertical)
-    prev = L.J[lidx(kForward ? -1 : T, l)];
-  else
-    prev = kForward ? hl : hr;
-  // Vertical 8-connected scans: lane 0's left neighbour and lane 63's right
-  // neighbour in the previous row are halo pixels; one LDS read per step
-  // supplies both (lane 0 reads column -1, lane 63 column 64, the others
-  // column 65, which holds zeros), and the in-tile diagonal neighbours come
-  // from the adjacent lanes with the max folded into the lane shift.
-  const int halo_col = l == 0 ? -1 : (l == T - 1 ? T : kZeroCol);
+  uint32_t prev = 0;
+  // Vertical 8-connected scans take the diagonal offers of the previous row
+  // from the adjacent lanes, with the max folded into a zero-filled lane
+  // shift (lanes 0 and 63 have no in-tile neighbour on one side).
 #pragma unroll 1
   for (int c = 0; c < T / kChunk; ++c) {
-    uint32_t vj[kChunk], vi[kChunk], vf[kChunk];
+    uint32_t vj[kChunk], vi[kChunk];
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
       const int at = kVertical ? lidx(s, l) : lidx(l, s);
       vj[k] = L.J[at];
       vi[k] = L.I[at];
-      if (kVertical && CONN == 8) vf[k] = L.J[lidx(kForward ? s - 1 : s + 1, halo_col)];
     }
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       uint32_t nv;
       if (kVertical && CONN == 8) {
         // J <= I throughout, so min(max(J, offers), I) needs no median
-        const uint32_t m = umax(from_right0(prev), umax(from_left0(prev), umax(umax(vj[k], prev), vf[k])));
+        const uint32_t m = umax(from_right0(prev), umax(from_left0(prev), umax(vj[k], prev)));
         nv = umin(m, vi[k]);
       } else {
         nv = umin(umax(vj[k], prev), vi[k]);
@@ -401,7 +425,8 @@ __device__ bool lds_settled(const WaveLds& L) {
 // forward (N^{+,0}), column-wise forward (N^{0,+}), row-wise backward
 // (N^{-,0}), column-wise backward (N^{0,-}).  Every step is one elementary
 // update J(p) <- max(J(p), J(q in the scan's neighbour set)) ^ I(p), so the
-// tile never leaves [J ^ I, rho_I(J)].  Halo pixels are sources only.  Four
+// tile never leaves [J ^ I, rho_I(J)].  Halo pixels are sources only, and
+// `fold_halo` applies all their offers before the first scan.  Four
 // consecutive scans that change nothing (one of each direction, in any
 // phase) mean every pixel already dominates each of its neighbours' offers:
 // the tile is stable.  The same holds when the one-pass test `lds_settled`
@@ -412,10 +437,8 @@ __device__ bool lds_settled(const WaveLds& L) {
 // locally stable; `changed` tells whether any scan changed a pixel.
 template <int CONN>
 __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed, int start = 0) {
-  const int l = lane();
-  const uint32_t hl = L.J[lidx(l, -1)], hr = L.J[lidx(l, T)];
   int quiet = 0;  // consecutive scans that changed nothing
-  changed = false;
+  changed = fold_halo<CONN>(L);
   // `start` picks the first scan (0 rows forward, 1 columns forward, 2 rows
   // backward, 3 columns backward), e.g. the one that carries a raised halo
   // side into the tile; the cyclic order is Algorithm 5's.
@@ -423,10 +446,10 @@ __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& change
     if ((n & 3) == 0) iters++;
     uint32_t ch = 0;
     switch ((start + n) & 3) {
-      case 0: scan<CONN, false, true>(L, hl, hr, ch); break;
-      case 1: scan<CONN, true, true>(L, hl, hr, ch); break;
-      case 2: scan<CONN, false, false>(L, hl, hr, ch); break;
-      default: scan<CONN, true, false>(L, hl, hr, ch); break;
+      case 0: scan<CONN, false, true>(L, ch); break;
+      case 1: scan<CONN, true, true>(L, ch); break;
+      case 2: scan<CONN, false, false>(L, ch); break;
+      default: scan<CONN, true, false>(L, ch); break;
     }
     if (ballot(ch != 0u) != 0u) {
       quiet = 0;
