@@ -73,7 +73,8 @@ typedef struct {
   int32_t profile;
   /* Cap on sweep iterations per tile in the reconstruction seed pass (the
    * number of raster/anti-raster scan pairs before the queue takes over; the
-   * paper varies the number of initial scans in Table 1; 0 = 2). */
+   * paper varies the number of initial scans in Table 1; 0 = 1 with
+   * 8-connectivity, 2 with 4-connectivity). */
   int32_t mr_seed_sweeps;
   int32_t reserved[6];
 } iwpp_options;

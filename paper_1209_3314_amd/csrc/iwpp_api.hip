@@ -270,9 +270,11 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.list_cap = (cap > 0 && (uint64_t)cap < g.ntiles) ? (uint32_t)cap : (uint32_t)g.ntiles;
     // Defaults from measurement on the 16384^2 workloads: a visit that stops
     // after two sweep iterations and is listed again is cheaper overall than
-    // one swept to stability, since neighbours keep changing its halo.
+    // one swept to stability, since neighbours keep changing its halo; the
+    // seed pass does one iteration with 8-connectivity, two with 4 (whose
+    // paths inside a tile are longer).
     a.max_sweeps = ctx->opt.mr_max_sweeps > 0 ? ctx->opt.mr_max_sweeps : 2;
-    a.seed_sweeps = ctx->opt.mr_seed_sweeps > 0 ? ctx->opt.mr_seed_sweeps : 2;
+    a.seed_sweeps = ctx->opt.mr_seed_sweeps > 0 ? ctx->opt.mr_seed_sweeps : (g.conn == 8 ? 1 : 2);
     a.flags = reinterpret_cast<uint32_t*>(scratch);
     a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * tb);
     a.unsettled = reinterpret_cast<uint32_t*>(scratch + 18 * tb);

@@ -325,8 +325,8 @@ __device__ bool fold_halo(WaveLds& L) {
 // values of the three (8-conn) or one (4-conn) upper/lower neighbours;
 // horizontal scans walk the columns with lane = row, using the previous
 // column.  Steps are loaded from LDS in chunks of kChunk so the wave pays one
-// LDS latency per chunk rather than per step; results are written back
-// unconditionally and increases accumulate in `ch`.
+// LDS latency per chunk rather than per step; a chunk's results are written
+// back if any of them changed, and increases accumulate in `ch`.
 constexpr int kChunk = 16;
 
 // Row scans (lane = row) on packed words: one step is a byte-selecting max of
@@ -373,11 +373,14 @@ __device__ __forceinline__ void row_scan(WaveLds& L, uint32_t& ch) {
       MR_HSTEP(w0, w1, i0, 3, 0); MR_HSTEP(w0, w0, i0, 2, 3); MR_HSTEP(w0, w0, i0, 1, 2); MR_HSTEP(w0, w0, i0, 0, 1);
       pw = w0;
     }
-    jp[0] = w0;
-    jp[1] = w1;
-    jp[2] = w2;
-    jp[3] = w3;
-    acc |= (o0 ^ w0) | (o1 ^ w1) | (o2 ^ w2) | (o3 ^ w3);
+    const uint32_t d = (o0 ^ w0) | (o1 ^ w1) | (o2 ^ w2) | (o3 ^ w3);
+    if (ballot(d != 0u) != 0u) {  // a chunk that changed nothing is not written back
+      jp[0] = w0;
+      jp[1] = w1;
+      jp[2] = w2;
+      jp[3] = w3;
+    }
+    acc |= d;
   }
   ch |= acc;
   wave_sync();
@@ -398,6 +401,7 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
 #pragma unroll 1
   for (int c = 0; c < T / kChunk; ++c) {
     uint32_t vj[kChunk], vi[kChunk];
+    const uint32_t ch0 = ch;
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
@@ -422,10 +426,12 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
       vj[k] = nv;
       prev = nv;
     }
+    if (ballot(ch != ch0) != 0u) {  // a chunk that changed nothing is not written back
 #pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-      const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
-      L.J[kVertical ? lidx(s, l) : lidx(l, s)] = (uint8_t)vj[k];
+      for (int k = 0; k < kChunk; ++k) {
+        const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
+        L.J[kVertical ? lidx(s, l) : lidx(l, s)] = (uint8_t)vj[k];
+      }
     }
     asm volatile("" ::: "memory");  // keep chunks apart: bounded register use
   }

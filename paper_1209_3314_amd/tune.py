@@ -22,10 +22,11 @@ from . import Context, _lib
 
 DEFAULTS = {"persistent_blocks": 0, "mr_max_sweeps": 0, "mr_seed_sweeps": 0, "mr_list_capacity": 0}
 
-# Candidate grids.  0 means the library default (device-filling grid, 2 sweeps).
+# Candidate grids.  0 means the library default (device-filling grid, default
+# sweep caps).
 GRID = {
     "recon": [{"persistent_blocks": pb, "mr_max_sweeps": ms, "mr_seed_sweeps": ss}
-              for pb in (0, 512, 768) for ms in (1, 0, 4) for ss in (1, 0, 4)],
+              for pb in (0, 512, 768) for ms in (1, 0, 4) for ss in (0, 1, 2, 4)],
     "edt": [{"persistent_blocks": pb} for pb in (0, 128, 256, 512)],
 }
 
