@@ -108,9 +108,10 @@ size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
   const int ts = op == IWPP_OP_RECON ? iwpp::kMrTile : iwpp::kEdtTile;
   const uint64_t t = (uint64_t)((h + ts - 1) / ts) * (uint64_t)((w + ts - 1) / ts);
   const uint64_t np = (uint64_t)h * (uint64_t)w;
-  // 5 tile words, and for recon a 256-byte border-column block per tile (+
-  // alignment slack of the per-group arrays is added by the caller)
-  return (size_t)(80 * t + 20 * 256 + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad : 256 * t) +
+  // 20 tile words, and per tile 256 bytes of recon border columns or 264 bytes
+  // of EDT visit stamps and change masks (+ alignment slack of the per-group
+  // arrays is added by the caller)
+  return (size_t)(80 * t + 20 * 256 + (op == IWPP_OP_EDT ? 8 * np + 2 * iwpp::kEdtStatePad + 264 * t : 256 * t) +
                   (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
 }
 
@@ -299,6 +300,8 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.flags = reinterpret_cast<uint32_t*>(scratch + 2 * fb);
     a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * fb + 2 * tb);
     a.tile_job = nj > 1 ? reinterpret_cast<uint32_t*>(scratch + 2 * fb + 18 * tb) : nullptr;
+    a.stamps = reinterpret_cast<uint32_t*>(scratch + 2 * fb + 19 * tb);
+    a.marks = reinterpret_cast<uint32_t*>(scratch + 2 * fb + 21 * tb);
     a.jobs = nj > 1 ? reinterpret_cast<const iwpp::EdtJob*>(tables + g.table_off) : nullptr;
     a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
     a.ovf = reinterpret_cast<uint32_t*>(fixed + kOffOvf);

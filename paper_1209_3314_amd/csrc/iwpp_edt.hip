@@ -161,17 +161,20 @@ __device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
 }
 
 // K rounds of the operator on the region in LDS, in place.  Round i
-// computes region rows and columns [i, RP-i) from round i-1's values: every
-// pixel in round 1, and in later rounds only the pixels with a neighbour (or
-// themselves) changed in round i-1 -- the others cannot change -- gathered
-// into a list from the previous round's change masks.  Each lane computes up
+// computes region rows and columns [i, RP-i) from round i-1's values, only at
+// the pixels with a neighbour (or themselves) changed in round i-1 -- the
+// others cannot change -- gathered into a list from the previous round's
+// change masks; for round 1 those are the previous step's last-round changes
+// over the region (`prev_step_changes`), or, with `full` (the first step),
+// every pixel is computed.  Each lane computes up
 // to kPerLane list pixels into registers and writes them after the whole
 // wave has read, so every read sees round i-1.  Pixels outside the image stay
 // none.  Accumulates the changed tile pixels (over the rounds), the zone mask
 // (bit 0: a tile pixel changed; bits 1..8: a change in round K within K
 // pixels of that side) and the last round (1..K) with a change.
 template <int CONN>
-__device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, uint32_t& zone, uint32_t& last) {
+__device__ void relax_steps(WaveLds& L, const TileRef& tr, bool full, uint32_t& changed, uint32_t& zone,
+                            uint32_t& last) {
   static_assert(RP <= 64, "one mask bit per region column");
   const EdtJob& j = tr.j;
   const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
@@ -180,9 +183,10 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
   for (int i = 1; i <= K; ++i) {
     unsigned long long* now = L.chg[i & 1];
     const unsigned long long* prev = L.chg[(i - 1) & 1];
-    // The active list of round i (round 1: implicit, every pixel of [1, RP-1)).
+    // The active list of round i (with `full`, round 1's is every pixel of
+    // [1, RP-1); otherwise chg[0] holds the previous step's last-round changes).
     uint32_t n;
-    if (i == 1) {
+    if (i == 1 && full) {
       n = (RP - 2) * (RP - 2);
     } else {
       const unsigned long long win = ((1ull << (RP - i)) - 1ull) & ~((1ull << i) - 1ull);  // columns [i, RP-i)
@@ -218,7 +222,7 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
       if ((uint32_t)(k * kWave) >= n) continue;  // wave-uniform
       if (idx >= n) continue;
       int row, col;
-      if (i == 1) {
+      if (i == 1 && full) {
         row = 1 + (int)(idx / (RP - 2));
         col = 1 + (int)(idx - (uint32_t)(row - 1) * (RP - 2));
       } else {
@@ -252,7 +256,7 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
       if ((uint32_t)(k * kWave) >= n) continue;
       if (idx >= n) continue;
       int row, col;
-      if (i == 1) {
+      if (i == 1 && full) {
         row = 1 + (int)(idx / (RP - 2));
         col = 1 + (int)(idx - (uint32_t)(row - 1) * (RP - 2));
       } else {
@@ -274,6 +278,45 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
     }
     wave_sync();
   }
+}
+
+// Region change mask (one 64-bit word per region row, bit = region column)
+// of the pixels that changed in the last round of step m-1, into `M`.  Every
+// such pixel lies in a tile visited in step m-1, which recorded its last-round
+// changes (`record_changes`) under that step's parity with stamp m-1; a tile
+// whose stamp differs did not change.  Lane = region row: three tile rows'
+// words (left neighbour, own column, right neighbour) per lane.
+__device__ void prev_step_changes(const EdtArgs& a, const TileRef& tr, uint32_t m, unsigned long long* M) {
+  const EdtJob& j = tr.j;
+  const int l = lane();
+  const uint32_t par = (m - 1u) & 1u;
+  unsigned long long v = 0;
+  const int y = tr.ty * TE - K + l;
+  if (l < RP && y >= 0 && y < j.h) {
+    const int ty = y / TE, ly = y - ty * TE;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int tx = tr.tx + dx;
+      if (tx < 0 || tx >= j.tiles_x) continue;
+      const uint32_t u = j.tile_base + (uint32_t)(ty * j.tiles_x + tx);
+      if (cload(a.stamps + (size_t)par * a.ntiles + u) != m - 1u) continue;
+      const unsigned long long w = cload(a.marks + ((size_t)par * a.ntiles + u) * 32u + (uint32_t)ly);
+      // region column rx <-> tile column rx - K - dx * TE
+      v |= dx < 0 ? (w >> (TE - K)) : (dx == 0 ? (w << K) : ((w & ((1ull << K) - 1ull)) << (K + TE)));
+    }
+  }
+  if (l < RP) M[l] = v;
+  wave_sync();
+}
+
+// Record this visit's last-round changes of the tile (rows and columns
+// [K, K + TE) of the round-K mask `M`) and stamp them with step m.
+__device__ void record_changes(const EdtArgs& a, uint32_t t, uint32_t m, const unsigned long long* M) {
+  const int l = lane();
+  const uint32_t par = m & 1u;
+  if (l < TE)
+    cstore(a.marks + ((size_t)par * a.ntiles + t) * 32u + (uint32_t)l, (uint32_t)((M[K + l] >> K) & ((1ull << TE) - 1ull)));
+  if (l == 0) cstore(a.stamps + (size_t)par * a.ntiles + t, m);
 }
 
 // Store the tile (region rows and columns [K, K + TE)) from S to `dst`.
@@ -436,8 +479,11 @@ __global__ __launch_bounds__(256, 4) void k_rounds(EdtArgs a) {
       if (lane() == 0) cstore(flg + t, 0u);
       const TileRef tr = tile_ref(a, t);
       load_region(rd, tr, L.F);
+      const bool full = m == 1u;  // the first step follows the initial state
+      if (!full) prev_step_changes(a, tr, m, L.chg[0]);
       uint32_t c = 0, zone = 0, lr = 0;
-      relax_steps<CONN>(L, tr, c, zone, lr);
+      relax_steps<CONN>(L, tr, full, c, zone, lr);
+      record_changes(a, t, m, L.chg[K & 1]);
       changed += c;
       visits++;
       uint32_t z = 0;
@@ -510,7 +556,7 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
       return -1;
     }
   }
-  if (zero_words(a.flags, 2ull * a.ntiles, stream) != 0) {
+  if (zero_words(a.flags, 2ull * a.ntiles, stream) != 0 || zero_words(a.stamps, 2ull * a.ntiles, stream) != 0) {
     *err = "flag reset launch failed";
     return -1;
   }

@@ -72,6 +72,8 @@ struct EdtArgs {
   uint32_t* feat1;            // [npix] round parity 1
   uint32_t* flags;            // [2][ntiles] tile on the round's list, per round parity
   uint32_t* lists;            // [2][8 shards][ntiles] tile lists per round parity
+  uint32_t* stamps;           // [2][ntiles] step of the tile's last visit, per step parity (0 = none)
+  uint32_t* marks;            // [2][ntiles][32] that visit's last-round change mask, one word per tile row
   uint32_t* counts;           // [3 round slots][8 shards][64] list fill levels (256 B apart)
   uint32_t* ovf;              // never set: a list holds each tile once
   GridBarrier* bar;

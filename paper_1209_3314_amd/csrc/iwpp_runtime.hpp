@@ -41,10 +41,11 @@ struct Group {
   }
   // Scratch layout (T = tiles, arrays of u32, each 256-byte aligned).
   // Recon: flags[2][T] | lists[2][8][T] | unsettled[T] | tile_job[T] | cols[T][256 B].
-  // EDT: feat0 | feat1 | flags[2][T] | lists[2][8][T] | tile_job[T].
+  // EDT: feat0 | feat1 | flags[2][T] | lists[2][8][T] | tile_job[T] | stamps[2][T] | marks[2][T][128 B].
   size_t scratch_bytes() const {
     const size_t tb = align256(ntiles * 4);
-    return op == IWPP_OP_EDT ? 2 * (align256(npix * 4) + iwpp::kEdtStatePad) + 19 * tb : 20 * tb + ntiles * 256;
+    return op == IWPP_OP_EDT ? 2 * (align256(npix * 4) + iwpp::kEdtStatePad) + 21 * tb + ntiles * 256
+                             : 20 * tb + ntiles * 256;
   }
 };
 
