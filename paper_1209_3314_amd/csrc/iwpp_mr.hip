@@ -413,9 +413,17 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
     for (int k = 0; k < kChunk; ++k) {
       uint32_t nv;
       if (kVertical && CONN == 8) {
-        // J <= I throughout, so min(max(J, offers), I) needs no median
-        const uint32_t m = umax(from_right0(prev), umax(from_left0(prev), umax(vj[k], prev)));
-        nv = umin(m, vi[k]);
+        // J <= I throughout, so min(max(J, offers), I) needs no median.  The
+        // two lane shifts are fused into the max (DPP with zero fill; the
+        // s_nop gives the two wait states a DPP read of a just-written
+        // register needs).
+        uint32_t ml, mr;
+        asm("s_nop 1\n\t"
+            "v_max_u32_dpp %0, %2, %3 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_max_u32_dpp %1, %2, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+            : "=&v"(ml), "=&v"(mr)
+            : "v"(prev), "v"(vj[k]));
+        nv = umin(umax(ml, mr), vi[k]);
       } else {
         nv = umin(umax(vj[k], prev), vi[k]);
       }
