@@ -165,7 +165,7 @@ __device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
 // the pixels with a neighbour (or themselves) changed in round i-1 -- the
 // others cannot change -- gathered into a list from the previous round's
 // change masks; for round 1 those are the previous step's last-round changes
-// over the region (`prev_step_changes`), or, with `full` (the first step),
+// over the region (`prev_step_issue` / `prev_step_finish`), or, with `full` (the first step),
 // every pixel is computed.  Each lane computes up
 // to kPerLane list pixels into registers and writes them after the whole
 // wave has read, so every read sees round i-1.  Pixels outside the image stay
@@ -281,29 +281,46 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, bool full, uint32_t& 
 }
 
 // Region change mask (one 64-bit word per region row, bit = region column)
-// of the pixels that changed in the last round of step m-1, into `M`.  Every
-// such pixel lies in a tile visited in step m-1, which recorded its last-round
-// changes (`record_changes`) under that step's parity with stamp m-1; a tile
-// whose stamp differs did not change.  Lane = region row: three tile rows'
-// words (left neighbour, own column, right neighbour) per lane.
-__device__ void prev_step_changes(const EdtArgs& a, const TileRef& tr, uint32_t m, unsigned long long* M) {
+// of the pixels that changed in the last round of step m-1.  Every such pixel
+// lies in a tile visited in step m-1, which recorded its last-round changes
+// (`record_changes`) under that step's parity with stamp m-1; a tile whose
+// stamp differs did not change.  Lane = region row: the stamps and row words
+// of three tiles (left neighbour, own column, right neighbour).  Split in two
+// so that the loads can be issued before the region load and waited for with
+// it.
+struct PrevChanges {
+  uint32_t stamp[3], word[3];
+};
+
+__device__ __forceinline__ void prev_step_issue(const EdtArgs& a, const TileRef& tr, uint32_t m, PrevChanges& pc) {
   const EdtJob& j = tr.j;
   const int l = lane();
   const uint32_t par = (m - 1u) & 1u;
-  unsigned long long v = 0;
   const int y = tr.ty * TE - K + l;
-  if (l < RP && y >= 0 && y < j.h) {
-    const int ty = y / TE, ly = y - ty * TE;
+  const bool row_ok = l < RP && y >= 0 && y < j.h;
+  const int ty = row_ok ? y / TE : 0, ly = row_ok ? y - ty * TE : 0;
 #pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int tx = tr.tx + dx;
-      if (tx < 0 || tx >= j.tiles_x) continue;
+  for (int d = 0; d < 3; ++d) {
+    const int tx = tr.tx + d - 1;
+    pc.stamp[d] = 0u;
+    pc.word[d] = 0u;
+    if (row_ok && tx >= 0 && tx < j.tiles_x) {
       const uint32_t u = j.tile_base + (uint32_t)(ty * j.tiles_x + tx);
-      if (cload(a.stamps + (size_t)par * a.ntiles + u) != m - 1u) continue;
-      const unsigned long long w = cload(a.marks + ((size_t)par * a.ntiles + u) * 32u + (uint32_t)ly);
-      // region column rx <-> tile column rx - K - dx * TE
-      v |= dx < 0 ? (w >> (TE - K)) : (dx == 0 ? (w << K) : ((w & ((1ull << K) - 1ull)) << (K + TE)));
+      pc.stamp[d] = cload(a.stamps + (size_t)par * a.ntiles + u);
+      pc.word[d] = cload(a.marks + ((size_t)par * a.ntiles + u) * 32u + (uint32_t)ly);
     }
+  }
+}
+
+__device__ __forceinline__ void prev_step_finish(uint32_t m, const PrevChanges& pc, unsigned long long* M) {
+  const int l = lane();
+  unsigned long long v = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (pc.stamp[d] != m - 1u) continue;
+    const unsigned long long w = pc.word[d];
+    // region column rx <-> tile column rx - K - (d - 1) * TE
+    v |= d == 0 ? (w >> (TE - K)) : (d == 1 ? (w << K) : ((w & ((1ull << K) - 1ull)) << (K + TE)));
   }
   if (l < RP) M[l] = v;
   wave_sync();
@@ -478,9 +495,11 @@ __global__ __launch_bounds__(256, 4) void k_rounds(EdtArgs a) {
       const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
       if (lane() == 0) cstore(flg + t, 0u);
       const TileRef tr = tile_ref(a, t);
-      load_region(rd, tr, L.F);
       const bool full = m == 1u;  // the first step follows the initial state
-      if (!full) prev_step_changes(a, tr, m, L.chg[0]);
+      PrevChanges pc;
+      if (!full) prev_step_issue(a, tr, m, pc);
+      load_region(rd, tr, L.F);
+      if (!full) prev_step_finish(m, pc, L.chg[0]);
       uint32_t c = 0, zone = 0, lr = 0;
       relax_steps<CONN>(L, tr, full, c, zone, lr);
       record_changes(a, t, m, L.chg[K & 1]);
