@@ -106,7 +106,9 @@ def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dic
     reconstruction, 30% EDT, conn 8); latency = end of the output download
     minus the scheduled arrival.  Capacity: `burst` requests submitted at
     once, pixels over the time until the last completes.  Every output is
-    compared with a plain single-image call of the same tile."""
+    compared with a plain single-image call of the same tile.  The capacity
+    burst runs again on a resident server (inputs already in HBM, outputs
+    per request on the device): the same loop without the PCIe copies."""
     from paper_1209_3314_amd import synth
 
     specs = synth.serve_pool(SERVE_POOL)
@@ -187,6 +189,45 @@ def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dic
             log(f"serve burst {mode}: {cap[mode]}")
         cap["throughput_batched_over_plain"] = round(cap["batched"]["mpix_s"] / max(cap["plain"]["mpix_s"], 1e-9), 3)
         res["capacity"] = cap
+        # Device-resident serving: the pool's inputs uploaded once, every request with
+        # device outputs of its own, no copies in the loop.
+        dinp = []
+        for j in jobs:
+            if j["op"] == "recon":
+                dinp.append({"op": "recon", "conn": j["conn"], "marker": j["marker"].to(dev), "mask": j["mask"].to(dev)})
+            else:
+                dinp.append({"op": "edt", "conn": j["conn"], "binary": j["binary"].to(dev)})
+
+        def run_resident(max_batch):
+            reqs = []
+            for _, idx in arr:
+                b = dinp[idx]
+                if b["op"] == "recon":
+                    reqs.append(dict(b, out=torch.empty_like(b["mask"])))
+                else:
+                    z = torch.empty(b["binary"].shape, dtype=torch.int32, device=dev)
+                    reqs.append(dict(b, sqdist=z, nearest=torch.empty_like(z)))
+            with iw.Server(ctx, hbm_budget_bytes=64 << 30, max_batch=max_batch, resident=True) as srv:
+                for r in reqs[:8]:  # warm-up
+                    srv.submit(r)
+                srv.drain(timeout_ms=120000)
+                torch.cuda.synchronize()
+                t0 = time.monotonic_ns()
+                tickets = [srv.submit(r, arrival_ns=t0) for r in reqs]
+                srv.drain(timeout_ms=600000)
+                lat = np.array([srv.poll(tk)[1] for tk in tickets])
+                st = srv.stats()
+            span = lat.max() / 1e3
+            exact = all(torch.equal(o.cpu(), rr) for r, (_, idx) in zip(reqs, arr)
+                        for o, rr in zip(outs(r), ref[idx]))
+            return lat, span, st, exact
+
+        rcap = {"requests": burst, "inputs": "device-resident (uploaded once), outputs per request on the device"}
+        for mode, mb in (("batched", 0), ("plain", 1)):
+            rcap[mode] = summary(arr, *run_resident(mb))
+            log(f"serve resident burst {mode}: {rcap[mode]}")
+        rcap["throughput_batched_over_plain"] = round(rcap["batched"]["mpix_s"] / max(rcap["plain"]["mpix_s"], 1e-9), 3)
+        res["capacity_resident"] = rcap
     return res
 
 

@@ -244,7 +244,14 @@ typedef struct {
   int64_t scratch_bytes;
   int32_t max_inflight; /* admitted jobs not yet complete (0 = 4096) */
   int32_t max_batch;    /* jobs per launch; 1 = one job per launch (0 = 512) */
-  int32_t reserved[6];
+  /* Nonzero: device-resident jobs.  Jobs then come with DEVICE buffers on the
+   * context's device (images already resident: no copies), the server
+   * allocates only the scratch area, admission is bounded by the in-flight
+   * limit, and a job is complete when its batch's computation is.  The
+   * outputs of jobs in flight together must not overlap any buffer of another
+   * of them (a batch containing such jobs fails). */
+  int32_t resident;
+  int32_t reserved[5];
 } iwpp_server_options;
 
 typedef struct {
@@ -265,15 +272,18 @@ enum { IWPP_JOB_QUEUED = 0, IWPP_JOB_ADMITTED = 1, IWPP_JOB_RUNNING = 2, IWPP_JO
 int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_server** out);
 
 /* Queue one job.  `job` has the layout of iwpp_run_batch's jobs but HOST
- * pointers (page-locked memory lets the copies overlap the computation); the
- * caller must not change the inputs or read the outputs before the job is
- * done.  `arrival_ns` is the request's arrival time on CLOCK_MONOTONIC (0 =
- * now); latency is measured from it.  Errors: IWPP_EINVAL (bad job, or one
- * that can never fit the budget), IWPP_EBUSY (stopping). */
+ * pointers (page-locked memory lets the copies overlap the computation), or
+ * device pointers on a resident server (each buffer is checked to be device
+ * memory of the context's device); the caller must not change the inputs or
+ * read the outputs before the job is done.  `arrival_ns` is the request's
+ * arrival time on CLOCK_MONOTONIC (0 = now); latency is measured from it.
+ * Errors: IWPP_EINVAL (bad job, one that can never fit the budget, or a
+ * buffer of the wrong kind), IWPP_EBUSY (stopping). */
 int32_t iwpp_server_submit(iwpp_server* server, const iwpp_job* job, int64_t arrival_ns, uint64_t* ticket);
 
 /* State of a ticket (IWPP_JOB_*) and, once done or failed, its latency:
- * completion of the output download minus arrival, in ms (else -1). */
+ * completion of the output download (resident: of the batch) minus arrival,
+ * in ms (else -1). */
 int32_t iwpp_server_poll(iwpp_server* server, uint64_t ticket, int32_t* state, double* latency_ms);
 
 /* Wait until every submitted job is done or failed (timeout_ms < 0: no

@@ -296,16 +296,20 @@ def _check_host(t, name: str, dtype):
 class Server:
     """A request loop on a context (iwpp_server_*): jobs with HOST tensors
     (pinned memory lets copies overlap compute) are admitted against a device
-    memory budget, run in continuous batches and copied back.  While it runs,
-    the context's other calls raise (busy)."""
+    memory budget, run in continuous batches and copied back; with
+    ``resident=True`` jobs come with tensors already on the context's device
+    and nothing is copied.  While it runs, the context's other calls raise
+    (busy)."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, scratch_bytes: int = 0, max_inflight: int = 0,
-                 max_batch: int = 0):
+                 max_batch: int = 0, resident: bool = False):
         o = _lib.ServerOptions()
         o.hbm_budget_bytes = int(hbm_budget_bytes)
         o.scratch_bytes = int(scratch_bytes)
         o.max_inflight = int(max_inflight)
         o.max_batch = int(max_batch)
+        o.resident = 1 if resident else 0
+        self.resident = bool(resident)
         h = ctypes.c_void_p()
         rc = ctx._lib.iwpp_server_start(ctx._h, ctypes.byref(o), ctypes.byref(h))
         if rc != _lib.IWPP_OK:
@@ -321,12 +325,18 @@ class Server:
     def submit(self, job: dict, arrival_ns: int = 0) -> int:
         """Queue a job: ``{"op": "recon", "marker", "mask", "out", "conn"}`` or
         ``{"op": "edt", "binary", "sqdist", "nearest", "conn"}`` with CPU
-        tensors; `arrival_ns` on time.monotonic_ns()'s clock (0 = now)."""
+        tensors (device tensors of the context's device for a resident
+        server); `arrival_ns` on time.monotonic_ns()'s clock (0 = now)."""
         torch = _torch()
         conn = int(job.get("conn", 8))
+        if self.resident:
+            dev = torch.device("cuda", self._ctx.device)
+            check = lambda t, name, dtype: _check_image(t, name, dtype, dev)  # noqa: E731
+        else:
+            check = _check_host
         if job["op"] == "recon":
             for k in ("marker", "mask", "out"):
-                _check_host(job[k], k, torch.uint8)
+                check(job[k], k, torch.uint8)
             if not (job["marker"].shape == job["mask"].shape == job["out"].shape):
                 raise ValueError("shapes differ")
             h, w = job["mask"].shape
@@ -334,9 +344,9 @@ class Server:
                          job["out"].data_ptr(), None)
             keep = (job["marker"], job["mask"], job["out"])
         elif job["op"] == "edt":
-            _check_host(job["binary"], "binary", torch.uint8)
-            _check_host(job["sqdist"], "sqdist", torch.int32)
-            _check_host(job["nearest"], "nearest", torch.int32)
+            check(job["binary"], "binary", torch.uint8)
+            check(job["sqdist"], "sqdist", torch.int32)
+            check(job["nearest"], "nearest", torch.int32)
             if not (job["binary"].shape == job["sqdist"].shape == job["nearest"].shape):
                 raise ValueError("shapes differ")
             h, w = job["binary"].shape

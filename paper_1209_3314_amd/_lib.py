@@ -43,7 +43,8 @@ class ServerOptions(ctypes.Structure):
         ("scratch_bytes", ctypes.c_int64),
         ("max_inflight", ctypes.c_int32),
         ("max_batch", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("resident", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 

@@ -2,17 +2,19 @@
 // device-memory budget and a slot limit, uploaded on a copy stream, run in
 // batches on a compute stream (all admitted jobs that are not yet running
 // form the next batch: continuous batching) and downloaded on a second copy
-// stream.  The paper's runtime hands independent tiles to whichever device
-// is free, first come first served (Sec. 4); here one device takes them in
-// batches, which fills it with many small tiles at once.
+// stream.  A resident server takes jobs whose images are already on the
+// device and skips the copies.  The paper's runtime hands independent tiles to
+// whichever device is free, first come first served (Sec. 4); here one device
+// takes them in batches, which fills it with many small tiles at once.
 //
 // Concurrency: one worker thread owns the device side (streams, arena,
 // batches); submit/poll/drain/stats take a mutex shared with it.  A batch
 // takes the admitted jobs whose uploads have finished; at most two batches are
 // queued on the compute stream, so the device goes from one batch to the next
 // without a host round trip while later arrivals still join the batch after,
-// and uploads, computation and downloads of successive batches overlap.  Batches share the context's fixed area and one scratch buffer:
-// they run one after another in stream order.
+// and uploads, computation and downloads of successive batches overlap.
+// Batches share the context's fixed area and one scratch buffer: they run one
+// after another in stream order.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
@@ -204,7 +206,7 @@ struct iwpp_server {
           j.done_ns = now;
           put_event(j.up);
           j.up = nullptr;
-          arena.release(j.off, j.bytes);
+          if (j.bytes) arena.release(j.off, j.bytes);
           if (ok)
             st.completed++;
           else
@@ -244,6 +246,21 @@ struct iwpp_server {
           continue;
         }
         if (st.admitted_now >= opt.max_inflight) break;
+      }
+      if (opt.resident) {  // device buffers already: nothing to allocate or upload
+        std::lock_guard<std::mutex> g(mu);
+        pending.pop_front();
+        j->off = 0;
+        j->bytes = 0;
+        j->dev = j->host;
+        j->up = nullptr;
+        j->state = IWPP_JOB_ADMITTED;
+        st.queued_now--;
+        st.admitted_now++;
+        if ((int64_t)scratch_cap > st.peak_bytes) st.peak_bytes = (int64_t)scratch_cap;
+        admitted.push_back(t);
+        progress = true;
+        continue;
       }
       const size_t bytes = job_buffer_bytes(j->host);
       size_t off = 0;
@@ -318,7 +335,7 @@ struct iwpp_server {
       std::lock_guard<std::mutex> g(mu);
       for (uint64_t t : admitted) {
         if ((int)dj.size() >= opt.max_batch) break;
-        const hipError_t q = hipEventQuery(jobs[t].up);
+        const hipError_t q = jobs[t].up ? hipEventQuery(jobs[t].up) : hipSuccess;
         if (q == hipErrorNotReady) break;
         if (q != hipSuccess) {
           (void)hipGetLastError();
@@ -376,7 +393,9 @@ struct iwpp_server {
       for (uint64_t t : tk) {
         SJob& j = jobs[t];
         const size_t np = (size_t)j.host.height * (size_t)j.host.width;
-        if (j.host.op == IWPP_OP_RECON) {
+        if (opt.resident) {
+          // outputs are the caller's device buffers
+        } else if (j.host.op == IWPP_OP_RECON) {
           ok = ok && hipMemcpyAsync(j.host.out0, j.dev.out0, np, hipMemcpyDeviceToHost, d2h) == hipSuccess;
         } else {
           ok = ok && hipMemcpyAsync(j.host.out0, j.dev.out0, 4 * np, hipMemcpyDeviceToHost, d2h) == hipSuccess &&
@@ -419,7 +438,7 @@ struct iwpp_server {
           j.done_ns = mono_ns();
           put_event(j.up);
           j.up = nullptr;
-          arena.release(j.off, j.bytes);
+          if (j.bytes) arena.release(j.off, j.bytes);
           st.failed++;
           st.admitted_now--;
           progress = true;
@@ -464,6 +483,7 @@ int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_se
   if (opt) o = *opt;
   if (o.hbm_budget_bytes < 0 || o.scratch_bytes < 0 || o.max_inflight < 0 || o.max_batch < 0)
     return fail(ctx, IWPP_EINVAL, "server_start: negative option");
+  if (o.resident != 0 && o.resident != 1) return fail(ctx, IWPP_EINVAL, "server_start: resident must be 0 or 1");
   if (o.hbm_budget_bytes == 0) o.hbm_budget_bytes = 64ll << 30;
   if (o.max_inflight == 0) o.max_inflight = 4096;
   if (o.max_batch == 0) o.max_batch = 512;
@@ -489,8 +509,8 @@ int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_se
   void* a = nullptr;
   void* sc = nullptr;
   void* pin = nullptr;
-  const size_t arena_bytes = s->budget - s->scratch_cap;
-  bool ok = hipMalloc(&a, arena_bytes) == hipSuccess;
+  const size_t arena_bytes = o.resident ? 0 : s->budget - s->scratch_cap;
+  bool ok = arena_bytes == 0 || hipMalloc(&a, arena_bytes) == hipSuccess;
   if (ok) s->arena_base = static_cast<uint8_t*>(a);
   ok = ok && hipMalloc(&sc, s->scratch_cap) == hipSuccess;
   if (ok) s->scratch = static_cast<uint8_t*>(sc);
@@ -536,10 +556,21 @@ int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_
     return fail(ctx, IWPP_EINVAL, "server_submit: EDT height and width must be <= 32767");
   if ((uint64_t)j.height * (uint64_t)j.width > 0xFFFFFFFFull)
     return fail(ctx, IWPP_EINVAL, "server_submit: image larger than 2^32 - 1 pixels");
-  const size_t need = job_buffer_bytes(j);
+  const size_t need = s->opt.resident ? 0 : job_buffer_bytes(j);
   const size_t sc = iwpp::rt::job_scratch_bytes(j.op, j.height, j.width) + 64 * 256;
   if (need > s->arena.size() || sc > s->scratch_cap)
     return fail(ctx, IWPP_EINVAL, "server_submit: the job can never fit the server's memory budget");
+  if (s->opt.resident) {
+    const void* bufs[4] = {j.in0, j.in1, j.out0, j.out1};
+    for (const void* b : bufs) {
+      if (!b) continue;
+      hipPointerAttribute_t at{};
+      const bool dev_ok = hipPointerGetAttributes(&at, b) == hipSuccess && at.type == hipMemoryTypeDevice &&
+                          at.device == ctx->device;
+      (void)hipGetLastError();
+      if (!dev_ok) return fail(ctx, IWPP_EINVAL, "server_submit: a resident server takes device buffers of its device");
+    }
+  }
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(ctx, IWPP_EBUSY, "server_submit: the server is stopping");

@@ -149,3 +149,59 @@ def test_busy_context_and_oversize_job(env):
     # usable again after stop
     a = torch.zeros((8, 8), dtype=torch.uint8, device=torch.device("cuda", 0))
     assert int(ctx.morph_recon(a, a.clone(), 8).sum()) == 0
+
+
+def device_jobs(torch, rng, n, sizes=(1, 400)):
+    """Jobs of a resident server: every job on device tensors of its own."""
+    hjobs, ref = host_jobs(torch, rng, n, sizes)
+    d = torch.device("cuda", 0)
+    djobs = []
+    for j in hjobs:
+        djobs.append({k: (v.to(d) if hasattr(v, "to") else v) for k, v in j.items()})
+    return djobs, ref
+
+
+def dev_outputs(j):
+    return [j["out"].cpu().numpy()] if j["op"] == "recon" else [j["sqdist"].cpu().numpy(), j["nearest"].cpu().numpy()]
+
+
+@pytest.mark.parametrize("seed,n,max_batch", [(51, 30, 0), (52, 10, 1)])
+def test_resident_mix_equals_alone_and_oracle(env, seed, n, max_batch):
+    torch, iw, ctx = env
+    jobs, ref = device_jobs(torch, np.random.default_rng(seed), n)
+    announce("serve resident", seed, n, max_batch)
+    srv = iw.Server(ctx, hbm_budget_bytes=256 << 20, max_batch=max_batch, resident=True)
+    try:
+        tickets = [srv.submit(j) for j in jobs]
+        srv.drain(timeout_ms=60000)
+        states = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+    finally:
+        srv.stop()
+    assert all(s == _lib.JOB_DONE for s, _ in states), states
+    assert st["completed"] == n and st["failed"] == 0
+    if max_batch == 1:
+        assert st["batches"] == n
+    torch.cuda.synchronize()
+    for j, r in zip(jobs, ref):
+        got = dev_outputs(j)
+        check_oracle(got, r)
+        a = alone(torch, ctx, j)
+        assert all(np.array_equal(x, y) for x, y in zip(got, a))
+
+
+def test_resident_rejects_host_buffers(env):
+    torch, iw, ctx = env
+    srv = iw.Server(ctx, hbm_budget_bytes=64 << 20, resident=True)
+    try:
+        h = torch.zeros((16, 16), dtype=torch.uint8).pin_memory()
+        with pytest.raises(ValueError):
+            srv.submit({"op": "recon", "conn": 8, "marker": h, "mask": h.clone(), "out": h.clone()})
+        # the library's own check, below the binding: host pointers are refused
+        m, o = h.clone().pin_memory(), h.clone().pin_memory()
+        j = _lib.Job(_lib.IWPP_OP_RECON, 8, 16, 16, h.data_ptr(), m.data_ptr(), o.data_ptr(), None)
+        import ctypes
+        t = ctypes.c_uint64()
+        assert srv._lib.iwpp_server_submit(srv._h, ctypes.byref(j), 0, ctypes.byref(t)) == _lib.IWPP_EINVAL
+    finally:
+        srv.stop()
