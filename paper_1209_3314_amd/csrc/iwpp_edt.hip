@@ -165,16 +165,15 @@ __device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
 // the pixels with a neighbour (or themselves) changed in round i-1 -- the
 // others cannot change -- gathered into a list from the previous round's
 // change masks; for round 1 those are the previous step's last-round changes
-// over the region (`prev_step_issue` / `prev_step_finish`), or, with `full` (the first step),
-// every pixel is computed.  Each lane computes up
+// over the region (`prev_step_issue` / `prev_step_finish`; for the first
+// step, the contour features recorded by `k_init`).  Each lane computes up
 // to kPerLane list pixels into registers and writes them after the whole
 // wave has read, so every read sees round i-1.  Pixels outside the image stay
 // none.  Accumulates the changed tile pixels (over the rounds), the zone mask
 // (bit 0: a tile pixel changed; bits 1..8: a change in round K within K
 // pixels of that side) and the last round (1..K) with a change.
 template <int CONN>
-__device__ void relax_steps(WaveLds& L, const TileRef& tr, bool full, uint32_t& changed, uint32_t& zone,
-                            uint32_t& last) {
+__device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, uint32_t& zone, uint32_t& last) {
   static_assert(RP <= 64, "one mask bit per region column");
   const EdtJob& j = tr.j;
   const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
@@ -183,12 +182,10 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, bool full, uint32_t& 
   for (int i = 1; i <= K; ++i) {
     unsigned long long* now = L.chg[i & 1];
     const unsigned long long* prev = L.chg[(i - 1) & 1];
-    // The active list of round i (with `full`, round 1's is every pixel of
-    // [1, RP-1); otherwise chg[0] holds the previous step's last-round changes).
+    // The active list of round i (for round 1, chg[0] holds the previous
+    // step's last-round changes over the region).
     uint32_t n;
-    if (i == 1 && full) {
-      n = (RP - 2) * (RP - 2);
-    } else {
+    {
       const unsigned long long win = ((1ull << (RP - i)) - 1ull) & ~((1ull << i) - 1ull);  // columns [i, RP-i)
       unsigned long long m = 0;
       if (l >= i && l < RP - i) {
@@ -221,15 +218,8 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, bool full, uint32_t& 
       const uint32_t idx = (uint32_t)(k * kWave + l);
       if ((uint32_t)(k * kWave) >= n) continue;  // wave-uniform
       if (idx >= n) continue;
-      int row, col;
-      if (i == 1 && full) {
-        row = 1 + (int)(idx / (RP - 2));
-        col = 1 + (int)(idx - (uint32_t)(row - 1) * (RP - 2));
-      } else {
-        const uint32_t e = L.list[idx];
-        row = (int)(e >> 8);
-        col = (int)(e & 0xffu);
-      }
+      const uint32_t e = L.list[idx];
+      const int row = (int)(e >> 8), col = (int)(e & 0xffu);
       const int qy = ry0 + row, qx = rx0 + col;
       if (qy < 0 || qy >= j.h || qx < 0 || qx >= j.w) continue;  // outside the image: stays none
       const uint32_t q = pack_yx(qy, qx);
@@ -255,15 +245,8 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, bool full, uint32_t& 
       const uint32_t idx = (uint32_t)(k * kWave + l);
       if ((uint32_t)(k * kWave) >= n) continue;
       if (idx >= n) continue;
-      int row, col;
-      if (i == 1 && full) {
-        row = 1 + (int)(idx / (RP - 2));
-        col = 1 + (int)(idx - (uint32_t)(row - 1) * (RP - 2));
-      } else {
-        const uint32_t e = L.list[idx];
-        row = (int)(e >> 8);
-        col = (int)(e & 0xffu);
-      }
+      const uint32_t e = L.list[idx];
+      const int row = (int)(e >> 8), col = (int)(e & 0xffu);
       uint32_t* c = &L.F[row * PE + col];
       const uint32_t old = c[0];
       if (res[k] == old) continue;
@@ -394,9 +377,11 @@ __device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const
 // Initial state (features carry themselves, everything else none) in both
 // buffers, the contour-feature count (Algorithm 6's initial queue), and the
 // first step's list: round 1 changes exactly the non-features next to a
-// feature, so their tiles and the neighbours within K pixels are listed.  One
-// wave per tile; the binary region (tile and one-pixel halo) is staged in
-// LDS.  The flags and counts must be zero beforehand.
+// feature, so their tiles and the neighbours within K pixels are listed.  The
+// contour features are every tile's step-0 change record, from which the
+// first step's round 1 takes its active pixels.  One wave per tile; the binary
+// region (tile and one-pixel halo) is staged in LDS.  The flags, counts and
+// stamps must be zero beforehand.
 template <int CONN>
 __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   constexpr int BR = TE + 2;  // binary region side
@@ -420,23 +405,32 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   const int x = lane() & 31, yb = lane() >> 5;
   const int qx = x0 + x;
   uint32_t contour = 0, zone = 0;
+  uint32_t* rec = a.marks + (size_t)t * 32u;  // step 0's record (parity 0; the stamps are zero)
   for (int y = yb; y < TE; y += 2) {
     const int qy = y0 + y;
-    if (x >= TE || qy >= j.h || qx >= j.w) continue;
-    const uint8_t* c = &B[(y + 1) * BP + x + 1];
-    const bool feat = c[0] != 0;
-    int nf = c[-BP] + c[BP] + c[-1] + c[1];
-    int nin = (qy > 0) + (qy + 1 < j.h) + (qx > 0) + (qx + 1 < j.w);
-    if (CONN == 8) {
-      nf += c[-BP - 1] + c[-BP + 1] + c[BP - 1] + c[BP + 1];
-      nin += (qy > 0 && qx > 0) + (qy > 0 && qx + 1 < j.w) + (qy + 1 < j.h && qx > 0) + (qy + 1 < j.h && qx + 1 < j.w);
+    bool ct = false;
+    if (x < TE && qy < j.h && qx < j.w) {
+      const uint8_t* c = &B[(y + 1) * BP + x + 1];
+      const bool feat = c[0] != 0;
+      int nf = c[-BP] + c[BP] + c[-1] + c[1];
+      int nin = (qy > 0) + (qy + 1 < j.h) + (qx > 0) + (qx + 1 < j.w);
+      if (CONN == 8) {
+        nf += c[-BP - 1] + c[-BP + 1] + c[BP - 1] + c[BP + 1];
+        nin += (qy > 0 && qx > 0) + (qy > 0 && qx + 1 < j.w) + (qy + 1 < j.h && qx > 0) + (qy + 1 < j.h && qx + 1 < j.w);
+      }
+      const uint32_t v = feat ? pack_yx(qy, qx) : kNone;
+      const size_t p = j.pix_base + (size_t)qy * (uint32_t)j.w + (uint32_t)qx;
+      a.feat0[p] = v;
+      a.feat1[p] = v;
+      ct = feat && nf < nin;  // a feature with a non-feature neighbour
+      contour += ct ? 1u : 0u;
+      if (!feat && nf > 0) zone |= 1u | zone_bits(y, x);
     }
-    const uint32_t v = feat ? pack_yx(qy, qx) : kNone;
-    const size_t p = j.pix_base + (size_t)qy * (uint32_t)j.w + (uint32_t)qx;
-    a.feat0[p] = v;
-    a.feat1[p] = v;
-    contour += (feat && nf < nin) ? 1u : 0u;  // a feature with a non-feature neighbour
-    if (!feat && nf > 0) zone |= 1u | zone_bits(y, x);
+    // Round 0's changes as round 1 sees them: only the contour features
+    // offer anything new (a feature keeps itself; a pixel away from every
+    // feature stays none).  Lanes 0..31 hold row y, lanes 32..63 row y + 1.
+    const uint64_t bm = ballot(ct);
+    if (lane() == 0 || lane() == 32) cstore(rec + y, lane() == 0 ? (uint32_t)bm : (uint32_t)(bm >> 32));
   }
   uint32_t tot = contour;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
@@ -495,13 +489,12 @@ __global__ __launch_bounds__(256, 4) void k_rounds(EdtArgs a) {
       const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
       if (lane() == 0) cstore(flg + t, 0u);
       const TileRef tr = tile_ref(a, t);
-      const bool full = m == 1u;  // the first step follows the initial state
       PrevChanges pc;
-      if (!full) prev_step_issue(a, tr, m, pc);
+      prev_step_issue(a, tr, m, pc);
       load_region(rd, tr, L.F);
-      if (!full) prev_step_finish(m, pc, L.chg[0]);
+      prev_step_finish(m, pc, L.chg[0]);
       uint32_t c = 0, zone = 0, lr = 0;
-      relax_steps<CONN>(L, tr, full, c, zone, lr);
+      relax_steps<CONN>(L, tr, c, zone, lr);
       record_changes(a, t, m, L.chg[K & 1]);
       changed += c;
       visits++;
