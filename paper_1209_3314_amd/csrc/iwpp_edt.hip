@@ -68,13 +68,35 @@ __device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > 
 // for q; f real or kNone).
 __device__ __forceinline__ uint32_t d2(uint32_t q, uint32_t f) {
   const s2 e = __builtin_elementwise_sub_sat(__builtin_bit_cast(s2, q), __builtin_bit_cast(s2, f));
-  return (uint32_t)__builtin_amdgcn_sdot2(e, e, 0, false);
+  // The three-operand dot product with a zero addend (the compiler's choice,
+  // the accumulating form, needs a register cleared first).
+  uint32_t r;
+  asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(__builtin_bit_cast(uint32_t, e)));
+  return r;
 }
 
-// Offer candidate f to the best (distance << 32 | feature) key of pixel q.
-__device__ __forceinline__ void offer(uint32_t q, uint32_t f, unsigned long long& best) {
-  const unsigned long long key = ((unsigned long long)d2(q, f) << 32) | f;
-  best = key < best ? key : best;
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// The lexicographically smallest (squared distance to q, feature) of the N
+// candidate features f[]: the smallest distance dm first, then the smallest
+// feature among the candidates at distance dm.  Distances are below 2^31, so
+// dm - d has its sign bit set exactly when d > dm; OR-ing that bit into the
+// feature puts every candidate farther than dm above every real feature
+// (real features are below 2^31; "none" has the bit already and is farthest
+// of all), and one more minimum picks the answer: 32-bit minima only, no
+// 64-bit key comparisons.
+template <int N>
+__device__ __forceinline__ uint32_t nearest_of(uint32_t q, const uint32_t (&f)[N]) {
+  uint32_t d[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = d2(q, f[i]);
+  uint32_t dm = d[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) dm = umin32(dm, d[i]);
+  uint32_t fm = 0xFFFFFFFFu;
+#pragma unroll
+  for (int i = 0; i < N; ++i) fm = umin32(fm, f[i] | ((dm - d[i]) & 0x80000000u));
+  return fm;
 }
 
 struct TileRef {
@@ -224,19 +246,13 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
       if (qy < 0 || qy >= j.h || qx < 0 || qx >= j.w) continue;  // outside the image: stays none
       const uint32_t q = pack_yx(qy, qx);
       const uint32_t* c = &L.F[row * PE + col];
-      const uint32_t old = c[0];
-      unsigned long long best = ((unsigned long long)d2(q, old) << 32) | old;
-      offer(q, c[-PE], best);
-      offer(q, c[PE], best);
-      offer(q, c[-1], best);
-      offer(q, c[1], best);
       if (CONN == 8) {
-        offer(q, c[-PE - 1], best);
-        offer(q, c[-PE + 1], best);
-        offer(q, c[PE - 1], best);
-        offer(q, c[PE + 1], best);
+        const uint32_t f[9] = {c[0], c[-PE], c[PE], c[-1], c[1], c[-PE - 1], c[-PE + 1], c[PE - 1], c[PE + 1]};
+        res[k] = nearest_of(q, f);
+      } else {
+        const uint32_t f[5] = {c[0], c[-PE], c[PE], c[-1], c[1]};
+        res[k] = nearest_of(q, f);
       }
-      res[k] = (uint32_t)best;
     }
     wave_sync();
     // Write back, recording the changes.
