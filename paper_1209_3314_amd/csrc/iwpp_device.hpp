@@ -90,6 +90,19 @@ __device__ __forceinline__ V uniform(const V& v) {
   __builtin_memcpy(&r, w, sizeof(V));
   return r;
 }
+// Inclusive prefix sum over the 64 lanes with DPP (no LDS round trips):
+// shifts by 1, 2, 4 and 8 inside each row of 16 lanes (zero-filled), then row
+// 0's total into row 1 and row 2's into row 3 (row_bcast:15), then the total of
+// rows 0-1 into rows 2-3 (row_bcast:31).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111 /* row_shr:1 */, 0xf, 0xf, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112 /* row_shr:2 */, 0xf, 0xf, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114 /* row_shr:4 */, 0xf, 0xf, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118 /* row_shr:8 */, 0xf, 0xf, true);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142 /* row_bcast:15 */, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143 /* row_bcast:31 */, 0xc, 0xf, false);
+  return x;
+}
 __device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
 }

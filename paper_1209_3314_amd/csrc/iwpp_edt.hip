@@ -216,12 +216,7 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
       }
       // exclusive prefix of the per-row counts over the lanes
       const uint32_t c = (uint32_t)__popcll(m);
-      uint32_t incl = c;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t v = (uint32_t)__shfl_up((int)incl, o);
-        if (l >= o) incl += v;
-      }
+      const uint32_t incl = wave_incl_sum(c);
       n = (uint32_t)readlane(incl, kWave - 1);
       uint32_t at = incl - c;
       while (m) {
@@ -518,8 +513,12 @@ __global__ __launch_bounds__(256, 4) void k_rounds(EdtArgs a) {
 #pragma unroll
       for (int b = 0; b < 9; ++b)
         if (ballot((zone >> b) & 1u)) z |= 1u << b;
-      uint32_t lw = lr;
-      for (int o = 32; o > 0; o >>= 1) lw = umax32(lw, (uint32_t)__shfl_xor((int)lw, o));
+      uint32_t lw = 0;  // the wave's last round with a change (lr is 0..K per lane)
+      for (uint32_t v = (uint32_t)K; v > 0u; --v)
+        if (ballot(lr >= v) != 0u) {
+          lw = v;
+          break;
+        }
       if (lw) last_round = umax32(last_round, (m - 1u) * (uint32_t)K + lw);
       store_tile(L.F, wr, tr);
       mark_reach(a, s, nx, tr, z);
