@@ -443,8 +443,7 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
     const uint64_t bm = ballot(ct);
     if (lane() == 0 || lane() == 32) cstore(rec + y, lane() == 0 ? (uint32_t)bm : (uint32_t)(bm >> 32));
   }
-  uint32_t tot = contour;
-  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+  const uint32_t tot = readlane(wave_incl_sum(contour), kWave - 1);
   uint32_t z = 0;
 #pragma unroll
   for (int b = 0; b < 9; ++b)
@@ -460,7 +459,7 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
 }
 
 template <int CONN>
-__global__ __launch_bounds__(256, 4) void k_rounds(EdtArgs a) {
+__global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
   __shared__ uint32_t cnt[kShards];
@@ -605,7 +604,7 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
     *err = "occupancy query failed";
     return -1;
   }
-  uint32_t blocks = persistent_grid(fn, per_cu, cus);
+  uint32_t blocks = persistent_grid(fn, per_cu, cus, 5);  // five workgroups of four waves fit a CU's registers and LDS
   if (persistent_blocks > 0 && (uint32_t)persistent_blocks < blocks) blocks = (uint32_t)persistent_blocks;
   EdtArgs args = a;
   void* kargs[] = {&args};
@@ -619,9 +618,9 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
   return 0;
 }
 
-uint32_t persistent_grid(const void* fn, int per_cu, int cus) {
+uint32_t persistent_grid(const void* fn, int per_cu, int cus, int max_per_cu) {
   hipFuncAttributes fa{};
-  int lim = per_cu < 4 ? per_cu : 4;
+  int lim = per_cu < max_per_cu ? per_cu : max_per_cu;
   if (hipFuncGetAttributes(&fa, fn) == hipSuccess && fa.sharedSizeBytes > 0) {
     const int by_lds = (int)((160u * 1024u) / (unsigned)fa.sharedSizeBytes);  // LDS per CU
     if (by_lds < lim) lim = by_lds;

@@ -117,10 +117,11 @@ int zero_words(uint32_t* p, size_t nwords, hipStream_t stream);
 
 // Workgroups for a cooperative (persistent) launch of `fn`: every one must be
 // resident at once, since they meet at grid barriers.  The runtime's occupancy
-// figure is capped by a 128 KiB LDS budget per CU and by 4 workgroups per CU;
-// grids sized from the raw figure (8 per CU for a 16 KiB kernel) were measured
-// not to be co-resident on MI355X, while these caps are.
-uint32_t persistent_grid(const void* fn, int per_cu, int cus);
+// figure is capped by the 160 KiB of LDS of a CU and by `max_per_cu`
+// workgroups per CU (4 unless the kernel's registers and LDS fit more); grids
+// sized from the raw figure (8 per CU for a 16 KiB kernel) were measured not
+// to be co-resident on MI355X, while these caps are.
+uint32_t persistent_grid(const void* fn, int per_cu, int cus, int max_per_cu = 4);
 
 // Launch a persistent kernel: a cooperative launch (the runtime checks that the
 // whole grid is resident), or a plain launch of the same grid while `s` is being
