@@ -117,3 +117,14 @@ def test_4k_workload(env):
     ex = oracle.edt_exact_sep(B)
     assert float((s != ex).mean()) <= 1e-4
     assert st["seeds"] > 0
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_few_features_long_fronts(env, conn):
+    """Three far-apart features: hundreds of rounds of thin fronts crossing
+    tiles, where every step depends on the change records of the step before."""
+    B = np.ones((900, 1100), np.uint8)
+    for y, x in [(450, 0), (0, 1099), (899, 555)]:
+        B[y, x] = 0
+    announce("edt few features", conn)
+    check(env, B, conn)

@@ -148,3 +148,33 @@ def test_round_timeline(env):
         assert 0.5 * ms * 1e3 <= sum(rt) <= 1.1 * ms * 1e3
     finally:
         ctx.close()
+
+
+def serpentine(h, w, pitch, rng):
+    """A one-pixel corridor that snakes down the image (rows every `pitch`
+    pixels joined at alternating ends), with mask levels falling along it, and
+    the marker raised only at its start: the flood has to cross every tile
+    many times, round after round."""
+    I = np.zeros((h, w), np.uint8)
+    path = []
+    for k, y in enumerate(range(1, h - 1, pitch)):
+        xs = range(1, w - 1) if k % 2 == 0 else range(w - 2, 0, -1)
+        path += [(y, x) for x in xs]
+        if y + pitch < h - 1:
+            xe = w - 2 if k % 2 == 0 else 1
+            path += [(yy, xe) for yy in range(y + 1, y + pitch)]
+    for i, (y, x) in enumerate(path):
+        I[y, x] = 255 - (i * 200) // len(path)
+    I = np.maximum(I, rng.integers(0, 3, (h, w), dtype=np.uint8))  # low noise off the corridor
+    J = np.zeros_like(I)
+    J[path[0]] = I[path[0]]
+    return J, I
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_serpentine_long_chain(env, conn):
+    J, I = serpentine(700, 700, 6, np.random.default_rng(5))
+    announce("mr serpentine", conn)
+    got, st = run(env, J, I, conn)
+    assert np.array_equal(got, oracle.mr_fh(J, I, conn))
+    assert st["rounds"] > 50  # the flood crosses tile borders round after round
