@@ -425,7 +425,8 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
             : "v"(prev), "v"(vj[k]));
         nv = umin(umax(ml, mr), vi[k]);
       } else {
-        nv = umin(umax(vj[k], prev), vi[k]);
+        // min(max(J, prev), I) is the median of the three because J <= I
+        asm("v_med3_u32 %0, %1, %2, %3" : "=v"(nv) : "v"(vj[k]), "v"(prev), "v"(vi[k]));
       }
       // Values only rise (J <= I holds throughout), so the sum of increases
       // is nonzero iff something changed; a sum keeps the compiler from
