@@ -380,9 +380,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(independent tiles would shard one per GPU; see DESIGN.md). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (independent tiles would "
+              "shard one per GPU, one image in horizontal bands). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     pool = gen = None
