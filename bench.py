@@ -359,8 +359,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tile batched leg")
     ap.add_argument("--batch-tiles", type=int, default=256, help="tiles in the batched leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--serve-rates", default="800", help="comma-separated request rates (per second)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0, help="trace length per rate")
+    ap.add_argument("--serve-rates", default="200,800,2000", help="comma-separated request rates (per second)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="trace length per rate")
     ap.add_argument("--serve-burst", type=int, default=256, help="requests of the capacity burst (0 = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for rocprofv3 byte counters)")
