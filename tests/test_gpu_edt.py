@@ -116,7 +116,15 @@ def test_4k_workload(env):
     s, _, _ = run(env, B, 8)
     ex = oracle.edt_exact_sep(B)
     assert float((s != ex).mean()) <= 1e-4
+    assert float(np.abs(np.sqrt(s.astype(np.float64)) - np.sqrt(ex.astype(np.float64))).max()) <= 1.0
     assert st["seeds"] > 0
+
+
+def test_4k_workload_conn4(env):
+    """The same workload with 4-connected propagation, every pixel."""
+    B = synth.workload_edt_4k()
+    announce("edt 4096^2 conn 4")
+    check(env, B, 4)
 
 
 @pytest.mark.parametrize("conn", [4, 8])
