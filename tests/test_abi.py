@@ -42,3 +42,39 @@ def test_binding_rejects_bad_tensors_before_the_library():
         iw.edt(torch.zeros((4, 4), dtype=torch.float32))
     with pytest.raises(TypeError):
         iw.edt([[0, 1]])
+
+
+# C struct name in include/iwpp.h -> ctypes mirror in the binding
+_MIRRORS = {"iwpp_options": "Options", "iwpp_stats": "Stats", "iwpp_kernel_time": "KernelTime",
+            "iwpp_job": "Job", "iwpp_server_options": "ServerOptions", "iwpp_server_stats": "ServerStats"}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding passes through the ABI has the header's size
+    and field offsets (a C program built with gcc against include/iwpp.h
+    prints them)."""
+    import shutil
+    import subprocess
+
+    from paper_1209_3314_amd import _lib
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "iwpp.h"', 'int main(void) {']
+    for cname, pyname in _MIRRORS.items():
+        st = getattr(_lib, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, pyname in _MIRRORS.items():
+        st = getattr(_lib, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(st), cname
+        for f, _ in st._fields_:
+            assert got[(cname, f)] == getattr(st, f).offset, (cname, f)
