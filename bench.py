@@ -537,6 +537,10 @@ def main():
     if pool is not None:
         pool.close()
         pool.join()
+    # Release the library's device memory and event records before the
+    # interpreter tears the process down.
+    torch.cuda.synchronize()
+    ctx.close()
 
     px = 2 * n_mr + n_edt
     value = px / (ms_per_step * 1e-3) / 1e6

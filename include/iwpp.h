@@ -126,14 +126,24 @@ const char* iwpp_last_error(const iwpp_ctx* ctx);
 
 /* Grayscale morphological reconstruction by dilation of mask I from marker J,
  * rho_I(J): the limit of J(p) <- max{J(q) : q in N_G(p) U {p}} ^ I(p) applied
- * until nothing changes (Sec. 2.1), computed as Algorithm 5 does: a seed pass
- * of scans, seed detection over the full neighbourhood, and queue-driven
- * propagation with atomic max updates.
+ * until nothing changes (Sec. 2.1).  The steps of Algorithm 5, re-planned for
+ * the GPU: a seed pass of raster and anti-raster scans swept to local
+ * stability inside 64x64 tiles held in LDS (one wave per tile), seed
+ * detection reduced to tests of the tile borders that rose, and propagation
+ * in rounds over a work list of tiles (the frontier, kept at tile
+ * granularity; a tile is listed when a border change can raise it) until the
+ * list is empty.  No pixel is updated atomically: a tile has one owner per
+ * round.  A bounded list (options.mr_list_capacity) drops, flags and rebuilds
+ * its frontier from the current image, as the paper's fixed-size global queue
+ * does on overflow (Sec. 3.2).
  *
  *   marker, mask : const uint8_t[height*width] (device)
  *   out          : uint8_t[height*width] (device); may alias marker (in place),
  *                  must not alias mask
- *   height,width : >= 1
+ *   height,width : >= 1; width <= 2^25 and at most 2^24 - 1 tiles of 64x64
+ *                  (about 68 G pixels): whole slides beyond 2^32 pixels are
+ *                  one call (the tile rounds carry the propagation across
+ *                  tiles, the border propagation of Sec. 4)
  *   conn         : 4 or 8
  * A marker above the mask is clamped first (the result is rho_I(min(J, I))).
  * Pixels outside the image are not neighbours.  The result is unique, so it is
@@ -160,8 +170,9 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
  *   binary        : const uint8_t[height*width] (device), 0 = feature
  *   sqdist        : int32_t[height*width] (device), squared distance
  *   nearest       : int32_t[height*width] (device), y*width + x of the feature
- *   height,width  : 1 .. 32767 (so squared distances fit in int32 and the
- *                   packed coordinates in 15 bits)
+ *   height,width  : 1 .. 46340 with (height-1)^2 + (width-1)^2 < 2^31, so
+ *                   every squared distance fits the int32 output; images with
+ *                   a side above 32767 use wider coordinate fields (slower)
  *   conn          : 4 or 8
  * If the image has no feature, sqdist and nearest are -1 everywhere.
  * Errors: IWPP_EINVAL (NULL pointer, dims out of range, conn not 4/8, outputs
@@ -277,9 +288,16 @@ int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_se
  * memory of the context's device); the caller must not change the inputs or
  * read the outputs before the job is done.  `arrival_ns` is the request's
  * arrival time on CLOCK_MONOTONIC (0 = now); latency is measured from it.
+ * `stream` (hipStream_t as void*, NULL = the default stream) is the caller's
+ * stream: an event is recorded on it at submit, and the job's work (its
+ * uploads; on a resident server its batch) waits for that event, so inputs
+ * that the caller's queued kernels are still writing, and output memory that
+ * its queued kernels still use, are safe to submit without synchronising.
  * Errors: IWPP_EINVAL (bad job, one that can never fit the budget, or a
- * buffer of the wrong kind), IWPP_EBUSY (stopping). */
-int32_t iwpp_server_submit(iwpp_server* server, const iwpp_job* job, int64_t arrival_ns, uint64_t* ticket);
+ * buffer of the wrong kind), IWPP_EBUSY (stopping), IWPP_EDEVICE (the event
+ * cannot be recorded on `stream`). */
+int32_t iwpp_server_submit(iwpp_server* server, const iwpp_job* job, int64_t arrival_ns, void* stream,
+                           uint64_t* ticket);
 
 /* State of a ticket (IWPP_JOB_*) and, once done or failed, its latency:
  * completion of the output download (resident: of the batch) minus arrival,
@@ -304,6 +322,19 @@ int32_t iwpp_server_stop(iwpp_server* server);
  * workgroup on the device's constant-rate clock.  Synchronises with the last
  * call's stream.  *n = phases written (at most max). */
 int32_t iwpp_round_times(iwpp_ctx* ctx, double* us, int32_t max, int32_t* n);
+
+/* iwpp_round_times plus the work of each phase: tiles[i] = tiles visited
+ * in phase i (reconstruction: every tile in the seed pass and in a full
+ * round after a work-list overflow, else the round's work list; distance
+ * transform: the step's work list).  At most 254 phases are recorded.
+ * Errors: IWPP_EINVAL (NULL arguments), IWPP_EDEVICE. */
+int32_t iwpp_round_work(iwpp_ctx* ctx, double* us, int64_t* tiles, int32_t max, int32_t* n);
+
+/* The same timeline for the last replay of a batch graph: the last
+ * persistent kernel of the graph (its last group).  Synchronises with the
+ * stream of that replay.  *n = 0 before the first replay.
+ * Errors: IWPP_EINVAL (NULL arguments), IWPP_EDEVICE. */
+int32_t iwpp_batch_graph_round_times(iwpp_graph* graph, double* us, int32_t max, int32_t* n);
 
 /* Per-kernel device times recorded since the previous read (needs
  * iwpp_options.profile).  Synchronises with every stream the recorded

@@ -181,6 +181,17 @@ class Context:
             self._err(rc)
         return [float(buf[i]) for i in range(n.value)]
 
+    def round_work(self) -> list:
+        """(device us, tiles visited) of each phase of the last call's
+        persistent kernel, phases as in round_times."""
+        buf = (ctypes.c_double * 256)()
+        tiles = (ctypes.c_int64 * 256)()
+        n = ctypes.c_int32()
+        rc = self._lib.iwpp_round_work(self._h, buf, tiles, 256, ctypes.byref(n))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return [(float(buf[i]), int(tiles[i])) for i in range(n.value)]
+
     def stats(self) -> dict:
         st = _lib.Stats()
         rc = self._lib.iwpp_get_stats(self._h, ctypes.byref(st))
@@ -253,13 +264,13 @@ class BatchGraph:
             raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
 
     def round_times(self) -> list:
-        """Device time (us) of each phase of the last call's persistent kernel:
-        reconstruction [seed pass, round 1, ...], EDT [step 1, ...]."""
+        """Device time (us) of each phase of the last persistent kernel of the
+        last replay (the graph's last group); [] before the first replay."""
         buf = (ctypes.c_double * 512)()
         n = ctypes.c_int32()
-        rc = self._lib.iwpp_round_times(self._h, buf, 512, ctypes.byref(n))
+        rc = self._lib.iwpp_batch_graph_round_times(self._h, buf, 512, ctypes.byref(n))
         if rc != _lib.IWPP_OK:
-            self._err(rc)
+            raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
         return [float(buf[i]) for i in range(n.value)]
 
     def stats(self) -> dict:
@@ -322,12 +333,16 @@ class Server:
     def _err(self, rc):
         raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
 
-    def submit(self, job: dict, arrival_ns: int = 0) -> int:
+    def submit(self, job: dict, arrival_ns: int = 0, stream=None) -> int:
         """Queue a job: ``{"op": "recon", "marker", "mask", "out", "conn"}`` or
         ``{"op": "edt", "binary", "sqdist", "nearest", "conn"}`` with CPU
         tensors (device tensors of the context's device for a resident
-        server); `arrival_ns` on time.monotonic_ns()'s clock (0 = now)."""
+        server); `arrival_ns` on time.monotonic_ns()'s clock (0 = now).  The
+        job waits for the work queued on `stream` (default: torch's current
+        stream of the context's device) before the submit."""
         torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(torch.device("cuda", self._ctx.device))
         conn = int(job.get("conn", 8))
         if self.resident:
             dev = torch.device("cuda", self._ctx.device)
@@ -356,7 +371,8 @@ class Server:
         else:
             raise ValueError("op must be 'recon' or 'edt'")
         t = ctypes.c_uint64()
-        rc = self._lib.iwpp_server_submit(self._h, ctypes.byref(j), int(arrival_ns), ctypes.byref(t))
+        rc = self._lib.iwpp_server_submit(self._h, ctypes.byref(j), int(arrival_ns), ctypes.c_void_p(stream.cuda_stream),
+                                          ctypes.byref(t))
         if rc != _lib.IWPP_OK:
             self._err(rc)
         self._keep[t.value] = keep

@@ -19,6 +19,8 @@ EXPORTED = (
     "iwpp_morph_recon_u8", "iwpp_edt", "iwpp_get_stats", "iwpp_profile_read", "iwpp_run_batch",
     "iwpp_set_options", "iwpp_round_times", "iwpp_server_start", "iwpp_server_submit", "iwpp_server_poll", "iwpp_server_drain",
     "iwpp_server_get_stats", "iwpp_server_stop", "iwpp_batch_graph_create", "iwpp_batch_graph_launch", "iwpp_batch_graph_stats", "iwpp_batch_graph_destroy",
+    "iwpp_batch_graph_round_times",
+    "iwpp_round_work",
 )
 IWPP_OP_RECON = 1
 IWPP_OP_EDT = 2
@@ -121,7 +123,7 @@ def load():
     lib.iwpp_run_batch.restype = i32
     lib.iwpp_server_start.argtypes = [vp, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
     lib.iwpp_server_start.restype = i32
-    lib.iwpp_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
+    lib.iwpp_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.c_int64, vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.iwpp_server_submit.restype = i32
     lib.iwpp_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.iwpp_server_poll.restype = i32
@@ -133,6 +135,9 @@ def load():
     lib.iwpp_server_stop.restype = i32
     lib.iwpp_round_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
     lib.iwpp_round_times.restype = i32
+    lib.iwpp_round_work.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32,
+                                    ctypes.POINTER(i32)]
+    lib.iwpp_round_work.restype = i32
     lib.iwpp_set_options.argtypes = [vp, ctypes.POINTER(Options)]
     lib.iwpp_set_options.restype = i32
     lib.iwpp_batch_graph_create.argtypes = [vp, ctypes.POINTER(Job), i32, ctypes.POINTER(vp)]
@@ -141,6 +146,8 @@ def load():
     lib.iwpp_batch_graph_launch.restype = i32
     lib.iwpp_batch_graph_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     lib.iwpp_batch_graph_stats.restype = i32
+    lib.iwpp_batch_graph_round_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
+    lib.iwpp_batch_graph_round_times.restype = i32
     lib.iwpp_batch_graph_destroy.argtypes = [vp]
     lib.iwpp_batch_graph_destroy.restype = None
     lib.iwpp_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]

@@ -115,6 +115,12 @@ size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
                   (op == IWPP_OP_RECON ? sizeof(iwpp::MrJob) : sizeof(iwpp::EdtJob)));
 }
 
+bool edt_dims_ok(int32_t h, int32_t w) {
+  if (h < 1 || w < 1 || h > 46340 || w > 46340) return false;
+  const int64_t a = h - 1, b = w - 1;
+  return a * a + b * b <= 0x7FFFFFFFll;
+}
+
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
   return x < y + nb && y < x + na;
@@ -158,7 +164,8 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
     if (j.op == IWPP_OP_RECON) {
       if (!j.in0 || !j.in1 || !j.out0 || j.out1)
         return fail(ctx, IWPP_EINVAL, at + "reconstruction needs in0 (marker), in1 (mask), out0 and no out1");
-      if (np > 0xFFFFFFFFull) return fail(ctx, IWPP_EINVAL, at + "image larger than 2^32 - 1 pixels");
+      // A tile's 66-row band of the image is addressed with 32-bit offsets.
+      if (j.width > (1 << 25)) return fail(ctx, IWPP_EINVAL, at + "reconstruction width must be <= 2^25");
       if (overlaps(j.out0, np, j.in1, np)) return fail(ctx, IWPP_EINVAL, at + "out must not alias mask");
       if (j.out0 != j.in0 && overlaps(j.out0, np, j.in0, np))
         return fail(ctx, IWPP_EINVAL, at + "out may equal marker but must not partially overlap it");
@@ -168,7 +175,8 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
     } else {
       if (!j.in0 || j.in1 || !j.out0 || !j.out1)
         return fail(ctx, IWPP_EINVAL, at + "EDT needs in0 (binary), out0 (sqdist), out1 (nearest) and no in1");
-      if (j.height > 32767 || j.width > 32767) return fail(ctx, IWPP_EINVAL, at + "EDT height and width must be <= 32767");
+      if (!edt_dims_ok(j.height, j.width))
+        return fail(ctx, IWPP_EINVAL, at + "EDT sides must be <= 46340 with (h-1)^2 + (w-1)^2 < 2^31");
       if (overlaps(j.out0, np * 4, j.out1, np * 4) || overlaps(j.out0, np * 4, j.in0, np) ||
           overlaps(j.out1, np * 4, j.in0, np))
         return fail(ctx, IWPP_EINVAL, at + "outputs must not alias each other or the input");
@@ -294,6 +302,9 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.job0 = g.edt[0];
     a.njobs = nj;
     a.npix = g.npix;
+    a.wide = 0;
+    for (const iwpp::EdtJob& e : g.edt)
+      if (e.h > 32767 || e.w > 32767) a.wide = 1;
     a.ntiles = (uint32_t)g.ntiles;
     a.feat0 = reinterpret_cast<uint32_t*>(scratch);
     a.feat1 = reinterpret_cast<uint32_t*>(scratch + fb);
@@ -350,6 +361,7 @@ int32_t run_plan(iwpp_ctx* ctx, const Plan& plan, hipStream_t st, int op_code) {
     first = false;
   }
   ctx->last_stream = st;
+  ctx->last_fixed = ctx->fixed;
   ctx->last_op = op_code;
   ctx->have_call = true;
   return IWPP_OK;
@@ -384,6 +396,31 @@ void fold_stats(const unsigned long long* h, int op, iwpp_stats* out) {
   out->updates = (int64_t)f[iwpp::kStatUpdates];
   out->overflow_restarts = (int64_t)f[iwpp::kStatRestarts];
   out->status = f[iwpp::kStatError] ? IWPP_EDEVICE : IWPP_OK;
+}
+
+// Round timeline words of a fixed area (see iwpp_round_times), after the
+// stream that last used it has finished.
+int32_t read_clock(iwpp_ctx* ctx, const uint8_t* fixed, hipStream_t st, double* us, int64_t* work, int32_t max,
+                   int32_t* n) {
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, "round_times: the last call's stream reported an error");
+  }
+  unsigned long long h[iwpp::kClockWords];
+  int khz = 0;
+  if (hipMemcpy(h, fixed + kOffClock, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0) {
+    (void)hipGetLastError();
+    return fail(ctx, IWPP_EDEVICE, "round_times: read failed");
+  }
+  const unsigned long long cnt = h[0] < (unsigned long long)iwpp::kClockStamps ? h[0] : iwpp::kClockStamps - 1;
+  int32_t w = 0;
+  for (unsigned long long i = 1; i < cnt && w < max; ++i, ++w) {
+    us[w] = (double)(h[i + 1] - h[i]) * 1000.0 / khz;
+    if (work) work[w] = (int64_t)h[iwpp::kClockStamps + w];
+  }
+  *n = w;
+  return IWPP_OK;
 }
 
 bool options_valid(const iwpp_options& o) {
@@ -631,22 +668,27 @@ int32_t iwpp_round_times(iwpp_ctx* ctx, double* us, int32_t max, int32_t* n) {
   if (!ctx->have_call) return IWPP_OK;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "round_times: cannot select the context's device");
-  if (hipStreamSynchronize(ctx->last_stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, "round_times: the last call's stream reported an error");
-  }
-  unsigned long long h[iwpp::kClockWords];
-  int khz = 0;
-  if (hipMemcpy(h, ctx->fixed + kOffClock, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0) {
-    (void)hipGetLastError();
-    return fail(ctx, IWPP_EDEVICE, "round_times: read failed");
-  }
-  const unsigned long long cnt = h[0] < (unsigned long long)iwpp::kClockWords ? h[0] : iwpp::kClockWords - 1;
-  int32_t w = 0;
-  for (unsigned long long i = 1; i < cnt && w < max; ++i, ++w) us[w] = (double)(h[i + 1] - h[i]) * 1000.0 / khz;
-  *n = w;
-  return IWPP_OK;
+  return read_clock(ctx, ctx->last_fixed, ctx->last_stream, us, nullptr, max, n);
+}
+
+int32_t iwpp_round_work(iwpp_ctx* ctx, double* us, int64_t* tiles, int32_t max, int32_t* n) {
+  if (!ctx) return IWPP_EINVAL;
+  if (!us || !tiles || !n || max < 0) return fail(ctx, IWPP_EINVAL, "round_work: NULL argument");
+  *n = 0;
+  if (!ctx->have_call) return IWPP_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, IWPP_EDEVICE, "round_work: cannot select the context's device");
+  return read_clock(ctx, ctx->last_fixed, ctx->last_stream, us, tiles, max, n);
+}
+
+int32_t iwpp_batch_graph_round_times(iwpp_graph* gr, double* us, int32_t max, int32_t* n) {
+  if (!gr) return IWPP_EINVAL;
+  if (!us || !n || max < 0) return fail(gr->ctx, IWPP_EINVAL, "batch_graph_round_times: NULL argument");
+  *n = 0;
+  if (!gr->launched) return IWPP_OK;
+  DeviceGuard g(gr->ctx->device);
+  if (!g.ok) return fail(gr->ctx, IWPP_EDEVICE, "batch_graph_round_times: cannot select the context's device");
+  return read_clock(gr->ctx, gr->fixed, gr->last_stream, us, nullptr, max, n);
 }
 
 int32_t iwpp_get_stats(iwpp_ctx* ctx, iwpp_stats* out) {
@@ -655,7 +697,7 @@ int32_t iwpp_get_stats(iwpp_ctx* ctx, iwpp_stats* out) {
   if (!ctx->have_call) return IWPP_OK;
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, IWPP_EDEVICE, "get_stats: cannot select the context's device");
-  return read_stats(ctx, ctx->fixed, ctx->last_stream, ctx->last_op, out);
+  return read_stats(ctx, ctx->last_fixed, ctx->last_stream, ctx->last_op, out);
 }
 
 }  // extern "C"

@@ -255,14 +255,19 @@ __device__ __forceinline__ void stage_append(WaveStageT<Item>& s, bool pred, Ite
 
 // ---- round timeline -----------------------------------------------------------
 // Workgroup 0 stamps the realtime clock (a constant-rate counter) at kernel
-// start and after every grid barrier: word 0 counts the stamps.  Costs one
-// store per round.
+// start and after every grid barrier into words 1..255 (word 0 counts the
+// stamps), and the work of each phase (tiles visited) into words 256 + phase.
+// Costs one or two stores per round.
+constexpr uint32_t kClockStamps = 256;
 __device__ __forceinline__ void clock_stamp(unsigned long long* clock, uint32_t& n) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && n + 1u < 512u) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n + 1u < kClockStamps) {
     n++;
     clock[n] = __builtin_amdgcn_s_memrealtime();
     clock[0] = n;
   }
+}
+__device__ __forceinline__ void round_work(unsigned long long* clock, uint32_t phase, uint32_t tiles) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && phase < kClockStamps) clock[kClockStamps + phase] = tiles;
 }
 
 // ---- sharded tile frontier --------------------------------------------------------

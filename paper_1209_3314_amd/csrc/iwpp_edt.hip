@@ -52,7 +52,6 @@ constexpr int kCPR = (RP + 3) / 4; // 16-byte chunks per region row
 constexpr int PE = 4 * kCPR;       // LDS row pitch (words)
 constexpr int kWavesPerBlock = 4;
 constexpr int kStageCap = 32;
-constexpr uint32_t kNone = 0x80008000u;
 constexpr uint32_t kMaxSteps = (1u << 20) / K;
 static_assert(RP - 2 <= 32, "a round's region row must fit 32 lanes");
 static_assert(K % 4 == 0, "region chunks must not straddle the image's left edge");
@@ -60,44 +59,87 @@ static_assert(K <= TE, "a change must reach no farther than the neighbouring til
 
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
 typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pack_yx(int y, int x) { return ((uint32_t)y << 16) | (uint32_t)x; }
 __device__ __forceinline__ uint32_t umax32(uint32_t a, uint32_t b) { return a > b ? a : b; }
-
-// Squared distance between packed points q and f (0 <= coordinates < 32767
-// for q; f real or kNone).
-__device__ __forceinline__ uint32_t d2(uint32_t q, uint32_t f) {
-  const s2 e = __builtin_elementwise_sub_sat(__builtin_bit_cast(s2, q), __builtin_bit_cast(s2, f));
-  // The three-operand dot product with a zero addend (the compiler's choice,
-  // the accumulating form, needs a register cleared first).
-  uint32_t r;
-  asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(__builtin_bit_cast(uint32_t, e)));
-  return r;
-}
-
 __device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
-// The lexicographically smallest (squared distance to q, feature) of the N
-// candidate features f[]: the smallest distance dm first, then the smallest
-// feature among the candidates at distance dm.  Distances are below 2^31, so
-// dm - d has its sign bit set exactly when d > dm; OR-ing that bit into the
-// feature puts every candidate farther than dm above every real feature
-// (real features are below 2^31; "none" has the bit already and is farthest
-// of all), and one more minimum picks the answer: 32-bit minima only, no
-// 64-bit key comparisons.
-template <int N>
-__device__ __forceinline__ uint32_t nearest_of(uint32_t q, const uint32_t (&f)[N]) {
-  uint32_t d[N];
+// Coordinate arithmetic of the state words, in two forms.
+//
+// Narrow (sides up to 32767): coordinates are signed 16-bit fields and "none"
+// is (-32768, -32768).  A squared distance is one saturating packed 16-bit
+// subtraction and one 2-term dot product; none's saturated distance,
+// 2 * 32767^2, exceeds that of any real feature, so it needs no special case.
+//
+// Wide (sides up to 46340, with (h-1)^2 + (w-1)^2 < 2^31 so that squared
+// distances fit the int32 output): coordinates are unsigned 16-bit fields and
+// none is all ones.  |dy|, |dx| come from packed maxima and minima, their
+// squares sum in an unsigned dot product (below 2^32 for such sides), and
+// none is given distance 2^32 - 1 explicitly.
+template <bool kWide>
+struct Coord;
+
+template <>
+struct Coord<false> {
+  static constexpr uint32_t none = 0x80008000u;
+  // Squared distance between q (real) and f (real or none).
+  __device__ static __forceinline__ uint32_t d2(uint32_t q, uint32_t f) {
+    const s2 e = __builtin_elementwise_sub_sat(__builtin_bit_cast(s2, q), __builtin_bit_cast(s2, f));
+    // The three-operand dot product with a zero addend (the compiler's choice,
+    // the accumulating form, needs a register cleared first).
+    uint32_t r;
+    asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(__builtin_bit_cast(uint32_t, e)));
+    return r;
+  }
+  // The lexicographically smallest (squared distance to q, feature) of the N
+  // candidate features f[]: the smallest distance dm first, then the smallest
+  // feature among the candidates at distance dm.  Distances are below 2^31,
+  // so dm - d has its sign bit set exactly when d > dm; OR-ing that bit into
+  // the feature puts every candidate farther than dm above every real feature
+  // (real features are below 2^31; none has the bit already and is farthest
+  // of all), and one more minimum picks the answer: 32-bit minima only, no
+  // 64-bit key comparisons.
+  template <int N>
+  __device__ static __forceinline__ uint32_t nearest(uint32_t q, const uint32_t (&f)[N]) {
+    uint32_t d[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) d[i] = d2(q, f[i]);
-  uint32_t dm = d[0];
+    for (int i = 0; i < N; ++i) d[i] = d2(q, f[i]);
+    uint32_t dm = d[0];
 #pragma unroll
-  for (int i = 1; i < N; ++i) dm = umin32(dm, d[i]);
-  uint32_t fm = 0xFFFFFFFFu;
+    for (int i = 1; i < N; ++i) dm = umin32(dm, d[i]);
+    uint32_t fm = 0xFFFFFFFFu;
 #pragma unroll
-  for (int i = 0; i < N; ++i) fm = umin32(fm, f[i] | ((dm - d[i]) & 0x80000000u));
-  return fm;
-}
+    for (int i = 0; i < N; ++i) fm = umin32(fm, f[i] | ((dm - d[i]) & 0x80000000u));
+    return fm;
+  }
+};
+
+template <>
+struct Coord<true> {
+  static constexpr uint32_t none = 0xFFFFFFFFu;
+  __device__ static __forceinline__ uint32_t d2(uint32_t q, uint32_t f) {
+    const u2 a = __builtin_bit_cast(u2, q), b = __builtin_bit_cast(u2, f);
+    const u2 e = __builtin_elementwise_max(a, b) - __builtin_elementwise_min(a, b);
+    const uint32_t r = __builtin_amdgcn_udot2(e, e, 0u, false);
+    return f == none ? 0xFFFFFFFFu : r;
+  }
+  // Lexicographic minimum: the smallest distance, then the smallest feature
+  // among the candidates at that distance (packed (y, x) order is index order).
+  template <int N>
+  __device__ static __forceinline__ uint32_t nearest(uint32_t q, const uint32_t (&f)[N]) {
+    uint32_t d[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = d2(q, f[i]);
+    uint32_t dm = d[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) dm = umin32(dm, d[i]);
+    uint32_t fm = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < N; ++i) fm = umin32(fm, d[i] == dm ? f[i] : 0xFFFFFFFFu);
+    return fm;
+  }
+};
 
 struct TileRef {
   EdtJob j;
@@ -137,11 +179,13 @@ struct WaveLds {
 };
 
 // Load the region of tile tr (rows and columns from K before the tile) from
-// `src` into S; pixels outside the image read as kNone.  kCPR 16-byte chunks
+// `src` into S; pixels outside the image read as none.  kCPR 16-byte chunks
 // per row, all issued with no branch in between so the wave waits for memory
 // once; a chunk cut by the image's right edge is loaded whole (the state
 // buffers are padded) and its outside words replaced.
+template <bool kWide>
 __device__ void load_region(const uint32_t* src, const TileRef& tr, uint32_t* S) {
+  constexpr uint32_t kNone = Coord<kWide>::none;
   const EdtJob& j = tr.j;
   const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
   const int row0 = ry0 > 0 ? ry0 : 0;
@@ -194,8 +238,9 @@ __device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
 // none.  Accumulates the changed tile pixels (over the rounds), the zone mask
 // (bit 0: a tile pixel changed; bits 1..8: a change in round K within K
 // pixels of that side) and the last round (1..K) with a change.
-template <int CONN>
+template <int CONN, bool kWide>
 __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, uint32_t& zone, uint32_t& last) {
+  constexpr uint32_t kNone = Coord<kWide>::none;
   static_assert(RP <= 64, "one mask bit per region column");
   const EdtJob& j = tr.j;
   const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
@@ -243,10 +288,10 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
       const uint32_t* c = &L.F[row * PE + col];
       if (CONN == 8) {
         const uint32_t f[9] = {c[0], c[-PE], c[PE], c[-1], c[1], c[-PE - 1], c[-PE + 1], c[PE - 1], c[PE + 1]};
-        res[k] = nearest_of(q, f);
+        res[k] = Coord<kWide>::nearest(q, f);
       } else {
         const uint32_t f[5] = {c[0], c[-PE], c[PE], c[-1], c[1]};
-        res[k] = nearest_of(q, f);
+        res[k] = Coord<kWide>::nearest(q, f);
       }
     }
     wave_sync();
@@ -393,7 +438,7 @@ __device__ __forceinline__ void mark_reach(const EdtArgs& a, WaveStage& s, const
 // first step's round 1 takes its active pixels.  One wave per tile; the binary
 // region (tile and one-pixel halo) is staged in LDS.  The flags, counts and
 // stamps must be zero beforehand.
-template <int CONN>
+template <int CONN, bool kWide>
 __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   constexpr int BR = TE + 2;  // binary region side
   constexpr int BP = BR + 2;  // byte pitch
@@ -429,7 +474,7 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
         nf += c[-BP - 1] + c[-BP + 1] + c[BP - 1] + c[BP + 1];
         nin += (qy > 0 && qx > 0) + (qy > 0 && qx + 1 < j.w) + (qy + 1 < j.h && qx > 0) + (qy + 1 < j.h && qx + 1 < j.w);
       }
-      const uint32_t v = feat ? pack_yx(qy, qx) : kNone;
+      const uint32_t v = feat ? pack_yx(qy, qx) : Coord<kWide>::none;
       const size_t p = j.pix_base + (size_t)qy * (uint32_t)j.w + (uint32_t)qx;
       a.feat0[p] = v;
       a.feat1[p] = v;
@@ -458,7 +503,7 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   shard_flush(st, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
 }
 
-template <int CONN>
+template <int CONN, bool kWide>
 __global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
   __shared__ WaveLds lds[kWavesPerBlock];
   __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
@@ -481,6 +526,7 @@ __global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
     uint32_t n = 0;
     for (int x = 0; x < kShards; ++x) n += cnt[x];
     if (n == 0u) break;
+    round_work(a.clock, m - 1u, n);
     if (m >= kMaxSteps) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;
@@ -501,10 +547,10 @@ __global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
       const TileRef tr = tile_ref(a, t);
       PrevChanges pc;
       prev_step_issue(a, tr, m, pc);
-      load_region(rd, tr, L.F);
+      load_region<kWide>(rd, tr, L.F);
       prev_step_finish(m, pc, L.chg[0]);
       uint32_t c = 0, zone = 0, lr = 0;
-      relax_steps<CONN>(L, tr, c, zone, lr);
+      relax_steps<CONN, kWide>(L, tr, c, zone, lr);
       record_changes(a, t, m, L.chg[K & 1]);
       changed += c;
       visits++;
@@ -535,12 +581,12 @@ __global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
     const uint32_t npx = (uint32_t)j.h * (uint32_t)j.w;
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += stride) {
       const uint32_t f = cload(fin + j.pix_base + p);
-      if (f == kNone) {
+      if (f == Coord<kWide>::none) {
         j.sqdist[p] = -1;
         j.nearest[p] = -1;
       } else {
         const uint32_t y = p / (uint32_t)j.w, x = p - y * (uint32_t)j.w;
-        j.sqdist[p] = (int32_t)d2(pack_yx((int)y, (int)x), f);
+        j.sqdist[p] = (int32_t)Coord<kWide>::d2(pack_yx((int)y, (int)x), f);
         j.nearest[p] = (int32_t)((f >> 16) * (uint32_t)j.w + (f & 0xffffu));
       }
     }
@@ -588,16 +634,21 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
   }
   const uint32_t init_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   rec->begin(4, stream);
-  if (conn == 8)
-    hipLaunchKernelGGL(k_init<8>, dim3(init_blocks), dim3(256), 0, stream, a);
+  if (conn == 8 && !a.wide)
+    hipLaunchKernelGGL((k_init<8, false>), dim3(init_blocks), dim3(256), 0, stream, a);
+  else if (conn == 8)
+    hipLaunchKernelGGL((k_init<8, true>), dim3(init_blocks), dim3(256), 0, stream, a);
+  else if (!a.wide)
+    hipLaunchKernelGGL((k_init<4, false>), dim3(init_blocks), dim3(256), 0, stream, a);
   else
-    hipLaunchKernelGGL(k_init<4>, dim3(init_blocks), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_init<4, true>), dim3(init_blocks), dim3(256), 0, stream, a);
   rec->end(stream);
   if (hipGetLastError() != hipSuccess) {
     *err = "EDT init launch failed";
     return -1;
   }
-  void* fn = conn == 8 ? reinterpret_cast<void*>(&k_rounds<8>) : reinterpret_cast<void*>(&k_rounds<4>);
+  void* fn = conn == 8 ? (a.wide ? reinterpret_cast<void*>(&k_rounds<8, true>) : reinterpret_cast<void*>(&k_rounds<8, false>))
+                       : (a.wide ? reinterpret_cast<void*>(&k_rounds<4, true>) : reinterpret_cast<void*>(&k_rounds<4, false>));
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) {

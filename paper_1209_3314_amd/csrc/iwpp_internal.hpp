@@ -67,6 +67,8 @@ struct EdtArgs {
   uint32_t* tile_job;         // [ntiles] image of each global tile when njobs > 1
   uint32_t njobs;
   uint32_t ntiles;
+  uint32_t wide;              // nonzero: wide coordinate fields (an image side above 32767)
+  uint32_t pad0;
   unsigned long long npix;    // total pixels over all images
   uint32_t* feat0;            // [npix] nearest feature (y << 16 | x), ~0 = none; round parity 0
   uint32_t* feat1;            // [npix] round parity 1
@@ -84,8 +86,9 @@ struct EdtArgs {
 // Bytes of the scratch areas the kernels expect.
 constexpr size_t kBarrierBytes = 4096;
 constexpr size_t kCountsBytes = 3 * 8 * 64 * 4;
-// Round timeline: word 0 = entries written, then realtime-clock stamps (kernel
-// start, then after every grid barrier) of one workgroup.
+// Round timeline: word 0 = stamps written, words 1..255 realtime-clock stamps
+// (kernel start, then after every grid barrier) of one workgroup, words
+// 256 + i the tiles visited in phase i.
 constexpr int kClockWords = 512;
 constexpr size_t kLostBytes = 2 * 64 * 4;
 constexpr size_t kStatsBytes = 8 * 16 * 8;

@@ -126,10 +126,15 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
                             uint32_t cols_bytes = 0, uint32_t t = 0) {
   const MrJob& a = tr.j;
   const int y0 = tr.ty * T, x0 = tr.tx * T;
-  const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
-  const __amdgpu_buffer_rsrc_t rj = make_rsrc(kSeed ? a.marker : a.out, total);
-  const __amdgpu_buffer_rsrc_t ri = make_rsrc(a.mask, total);
-  const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, total);
+  // Buffer resources over the image rows the region touches, [yb, ye): offsets
+  // stay 32-bit whatever the image size (a 66-row band of a row of up to 2^31
+  // pixels), so images beyond 2^32 pixels are addressed like small ones.
+  const int yb = y0 > 0 ? y0 - 1 : 0, ye = y0 + T + 1 < a.h ? y0 + T + 1 : a.h;
+  const uint32_t band = (uint32_t)(ye - yb) * (uint32_t)a.w;
+  const size_t base = (size_t)yb * (size_t)(uint32_t)a.w;
+  const __amdgpu_buffer_rsrc_t rj = make_rsrc((kSeed ? a.marker : a.out) + base, band);
+  const __amdgpu_buffer_rsrc_t ri = make_rsrc(a.mask + base, band);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out + base, band);
   const int rem = a.w - x0;  // image columns from this tile's first column on
   const int cp = (rem < T && (rem & 15) != 0) ? rem >> 4 : -1;  // the cut chunk column, if any
   constexpr int kMain = kRows * 4, kHalo = kRows * 2;
@@ -142,7 +147,7 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
     const int c = idx & 3;
     const int y = y0 - 1 + (idx >> 2), xs = x0 + 16 * c;
     const bool ok = idx < kMain && y >= 0 && y < a.h && xs + 16 <= a.w;
-    const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)xs : kOutside;
+    const uint32_t off = ok ? (uint32_t)(y - yb) * (uint32_t)a.w + (uint32_t)xs : kOutside;
     vj[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rj, off, 0, kSc1));
     vi[k] = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ri, off, 0, kSc1));
   }
@@ -150,7 +155,7 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
   if (kSeed && fresh_top) {  // wave-uniform; lanes 0..3 hold the row above
     const int y = y0 - 1, xs = x0 + 16 * (lane() & 3);
     const bool ok = lane() < 4 && y >= 0 && xs + 16 <= a.w;
-    const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)xs : kOutside;
+    const uint32_t off = ok ? (uint32_t)(y - yb) * (uint32_t)a.w + (uint32_t)xs : kOutside;
     vtop = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(ro, off, 0, kSc1));
     if (lane() < 4) vj[0] = vtop;
   }
@@ -161,7 +166,7 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
       const int y = y0 - 1 + (idx >> 1);
       const int x = (idx & 1) ? x0 + T : x0 - 1;
       const bool ok = idx < kHalo && y >= 0 && y < a.h && x >= 3 && x < a.w;
-      const uint32_t off = ok ? (uint32_t)y * (uint32_t)a.w + (uint32_t)(x - 3) : kOutside;
+      const uint32_t off = ok ? (uint32_t)(y - yb) * (uint32_t)a.w + (uint32_t)(x - 3) : kOutside;
       hj[k] = __builtin_amdgcn_raw_buffer_load_b32(rj, off, 0, kSc1);
       hi[k] = __builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, kSc1);
     }
@@ -233,7 +238,7 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
       uint32_t bj[15], bi[15];
 #pragma unroll
       for (int b = 0; b < 15; ++b) {
-        const uint32_t off = (row_ok && b < nb) ? (uint32_t)y * (uint32_t)a.w + (uint32_t)(xs + b) : kOutside;
+        const uint32_t off = (row_ok && b < nb) ? (uint32_t)(y - yb) * (uint32_t)a.w + (uint32_t)(xs + b) : kOutside;
         bj[b] = __builtin_amdgcn_raw_buffer_load_b8(rj, off, 0, kSc1);
         bi[b] = __builtin_amdgcn_raw_buffer_load_b8(ri, off, 0, kSc1);
       }
@@ -255,15 +260,16 @@ __device__ void load_region(const TileRef& tr, WaveLds& L, bool fresh_top = fals
 __device__ void store_tile(const TileRef& tr, const WaveLds& L) {
   const MrJob& a = tr.j;
   const int y0 = tr.ty * T, x0 = tr.tx * T;
-  const uint32_t total = (uint32_t)a.h * (uint32_t)a.w;
-  const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, total);
+  const int ye = y0 + T < a.h ? y0 + T : a.h;  // the tile's rows, as a band of their own (see load_region)
+  const __amdgpu_buffer_rsrc_t ro =
+      make_rsrc(a.out + (size_t)y0 * (size_t)(uint32_t)a.w, (uint32_t)(ye - y0) * (uint32_t)a.w);
   for (int idx = lane(); idx < T * 4; idx += kWave) {
     const int ry = idx >> 2, c = idx & 3;
     const int y = y0 + ry, xs = x0 + c * 16;
     if (y >= a.h || xs >= a.w) continue;
     const uint32_t* s = reinterpret_cast<const uint32_t*>(&L.J[lidx(ry, c * 16)]);
     v4u v = {s[0], s[1], s[2], s[3]};
-    const uint32_t off = (uint32_t)y * (uint32_t)a.w + (uint32_t)xs;
+    const uint32_t off = (uint32_t)ry * (uint32_t)a.w + (uint32_t)xs;
     if (xs + 16 <= a.w) {
       __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, v), ro, off, 0, kSc1);
     } else {
@@ -310,6 +316,9 @@ __device__ bool fold_halo(WaveLds& L) {
   L.J[lidx(0, l)] = (uint8_t)nt;
   L.J[lidx(T - 1, l)] = (uint8_t)nb;
   up |= nt != jt || nb != jb;
+  // The column phase reads corners that other lanes wrote in the row phase
+  // (lane 63 wrote (0, 63), lane 0 wrote (63, 0)): order the two phases.
+  wave_sync();
   const uint32_t hl = offer(l - 1, -1, l, -1, l + 1, -1), hr = offer(l - 1, T, l, T, l + 1, T);
   const uint32_t jl = L.J[lidx(l, 0)], il = L.I[lidx(l, 0)], jr = L.J[lidx(l, T - 1)], ir = L.I[lidx(l, T - 1)];
   const uint32_t nl = umax(jl, umin(hl, il)), nr = umax(jr, umin(hr, ir));
@@ -817,6 +826,7 @@ __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
     }
     shard_flush(s, nx.list, nx.count, nx.cap, nx.flags, nx.lost);
   }
+  round_work(a.clock, 0u, a.ntiles);
   bool ok = grid_barrier(a.bar, gen, a.stats);
   clock_stamp(a.clock, nclk);
   for (uint32_t r = 1; ok; ++r) {
@@ -830,6 +840,7 @@ __global__ __launch_bounds__(256, 4) void k_propagate(MrArgs a) {
     for (int x = 0; x < kShards; ++x) n += cnt[x];
     const bool full = lost_sh != 0u;
     if (!full && n == 0u) break;
+    round_work(a.clock, r, full ? a.ntiles : n);
     if (r >= kMaxRounds) {  // safety limit: report instead of spinning on a logic error
       if (blockIdx.x == 0 && threadIdx.x == 0) stat_add(a.stats, kStatError, 1ull);
       break;

@@ -55,6 +55,10 @@ struct Plan {
   size_t table_bytes = 0;    // sum over groups
 };
 
+// Sides the distance transform accepts: at most 46340 each, and every squared
+// distance ((h-1)^2 + (w-1)^2 at most) below 2^31 so it fits the int32 output.
+bool edt_dims_ok(int32_t h, int32_t w);
+
 // Scratch bytes one image adds to a group (upper bound, used for admission).
 size_t job_scratch_bytes(int op, int32_t h, int32_t w);
 
@@ -78,6 +82,7 @@ struct iwpp_ctx {
   uint8_t* scratch = nullptr;  // growable: group scratch, then job tables
   size_t scratch_bytes = 0;
   hipStream_t last_stream = nullptr;
+  uint8_t* last_fixed = nullptr;  // fixed area of the last call (the context's, or the static one)
   int last_op = 0;
   bool have_call = false;
   iwpp_server* server = nullptr;  // a running server owns the context

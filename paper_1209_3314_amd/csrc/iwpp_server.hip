@@ -107,6 +107,7 @@ struct SJob {
   size_t off = 0, bytes = 0;
   iwpp_job dev{};             // the same job on device buffers
   hipEvent_t up = nullptr;    // recorded after the job's uploads
+  hipEvent_t ready = nullptr; // recorded on the caller's stream at submit
 };
 
 struct Batch {
@@ -146,6 +147,7 @@ struct iwpp_server {
   std::condition_variable cv;
   std::deque<SJob> jobs;  // index = ticket
   std::deque<uint64_t> pending;
+  std::vector<hipEvent_t> ready_pool;  // submit-side events (under mu)
   bool stop = false;
   std::string error;
   iwpp_server_stats st{};
@@ -206,6 +208,8 @@ struct iwpp_server {
           j.done_ns = now;
           put_event(j.up);
           j.up = nullptr;
+          if (j.ready) ready_pool.push_back(j.ready);
+          j.ready = nullptr;
           if (j.bytes) arena.release(j.off, j.bytes);
           if (ok)
             st.completed++;
@@ -237,6 +241,8 @@ struct iwpp_server {
         j = &jobs[t];
         if (broken) {
           pending.pop_front();
+          if (j->ready) ready_pool.push_back(j->ready);
+          j->ready = nullptr;
           j->state = IWPP_JOB_FAILED;
           j->done_ns = mono_ns();
           st.failed++;
@@ -268,20 +274,21 @@ struct iwpp_server {
       const size_t np = (size_t)j->host.height * (size_t)j->host.width;
       uint8_t* base = arena_base + off;
       iwpp_job d = j->host;
-      bool ok = true;
+      // The copies wait for the caller's work queued before the submit.
+      bool ok = hipStreamWaitEvent(h2d, j->ready, 0) == hipSuccess;
       if (d.op == IWPP_OP_RECON) {
         uint8_t* mask = base;
         uint8_t* marker = base + align256(np);  // overwritten by the result
         d.in1 = mask;
         d.in0 = marker;
         d.out0 = marker;
-        ok = hipMemcpyAsync(mask, j->host.in1, np, hipMemcpyHostToDevice, h2d) == hipSuccess &&
+        ok = ok && hipMemcpyAsync(mask, j->host.in1, np, hipMemcpyHostToDevice, h2d) == hipSuccess &&
              hipMemcpyAsync(marker, j->host.in0, np, hipMemcpyHostToDevice, h2d) == hipSuccess;
       } else {
         d.in0 = base;
         d.out0 = base + align256(np);
         d.out1 = base + align256(np) + align256(4 * np);
-        ok = hipMemcpyAsync(base, j->host.in0, np, hipMemcpyHostToDevice, h2d) == hipSuccess;
+        ok = ok && hipMemcpyAsync(base, j->host.in0, np, hipMemcpyHostToDevice, h2d) == hipSuccess;
       }
       hipEvent_t up = ok ? get_event() : nullptr;
       ok = ok && up && hipEventRecord(up, h2d) == hipSuccess;
@@ -376,6 +383,13 @@ struct iwpp_server {
     iwpp::rt::pack_tables(plan, slot_tables(slot));
     iwpp::Recorder off;
     bool ok = b.done && b.down;
+    if (opt.resident) {
+      // A resident job's buffers are the caller's: its batch waits for the
+      // work the caller queued on its stream before the submit (inputs being
+      // written, earlier users of the output memory).
+      std::lock_guard<std::mutex> g(mu);
+      for (size_t i = 0; i < n && ok; ++i) ok = hipStreamWaitEvent(comp, jobs[tk[i]].ready, 0) == hipSuccess;
+    }
     if (ok && plan.table_bytes)
       ok = hipMemcpyAsync(tables, slot_tables(slot), plan.table_bytes, hipMemcpyHostToDevice, comp) == hipSuccess;
     bool first = true;
@@ -438,6 +452,8 @@ struct iwpp_server {
           j.done_ns = mono_ns();
           put_event(j.up);
           j.up = nullptr;
+          if (j.ready) ready_pool.push_back(j.ready);
+          j.ready = nullptr;
           if (j.bytes) arena.release(j.off, j.bytes);
           st.failed++;
           st.admitted_now--;
@@ -459,6 +475,9 @@ namespace {
 
 void free_server(iwpp_server* s) {
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : s->ready_pool) (void)hipEventDestroy(e);
+  for (SJob& j : s->jobs)
+    if (j.ready) (void)hipEventDestroy(j.ready);
   if (s->pinned) (void)hipHostFree(s->pinned);
   if (s->h2d) (void)hipStreamDestroy(s->h2d);
   if (s->comp) (void)hipStreamDestroy(s->comp);
@@ -539,7 +558,7 @@ int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_se
   return IWPP_OK;
 }
 
-int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_ns, uint64_t* ticket) {
+int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_ns, void* stream, uint64_t* ticket) {
   using iwpp::rt::fail;
   if (!s) return IWPP_EINVAL;
   iwpp_ctx* ctx = s->ctx;
@@ -552,8 +571,8 @@ int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_
     return fail(ctx, IWPP_EINVAL, "server_submit: reconstruction needs in0, in1, out0 and no out1");
   if (j.op == IWPP_OP_EDT && (!j.in0 || j.in1 || !j.out0 || !j.out1))
     return fail(ctx, IWPP_EINVAL, "server_submit: EDT needs in0, out0, out1 and no in1");
-  if (j.op == IWPP_OP_EDT && (j.height > 32767 || j.width > 32767))
-    return fail(ctx, IWPP_EINVAL, "server_submit: EDT height and width must be <= 32767");
+  if (j.op == IWPP_OP_EDT && !iwpp::rt::edt_dims_ok(j.height, j.width))
+    return fail(ctx, IWPP_EINVAL, "server_submit: EDT sides must be <= 46340 with (h-1)^2 + (w-1)^2 < 2^31");
   if ((uint64_t)j.height * (uint64_t)j.width > 0xFFFFFFFFull)
     return fail(ctx, IWPP_EINVAL, "server_submit: image larger than 2^32 - 1 pixels");
   const size_t need = s->opt.resident ? 0 : job_buffer_bytes(j);
@@ -571,10 +590,26 @@ int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_
       if (!dev_ok) return fail(ctx, IWPP_EINVAL, "server_submit: a resident server takes device buffers of its device");
     }
   }
+  iwpp::rt::DeviceGuard dg(ctx->device);
+  if (!dg.ok) return fail(ctx, IWPP_EDEVICE, "server_submit: cannot select the context's device");
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(ctx, IWPP_EBUSY, "server_submit: the server is stopping");
+    hipEvent_t ready = nullptr;
+    if (!s->ready_pool.empty()) {
+      ready = s->ready_pool.back();
+      s->ready_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, IWPP_EDEVICE, "server_submit: event creation failed");
+    }
+    if (hipEventRecord(ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+      (void)hipGetLastError();
+      s->ready_pool.push_back(ready);
+      return fail(ctx, IWPP_EDEVICE, "server_submit: cannot record on the caller's stream");
+    }
     SJob sj;
+    sj.ready = ready;
     sj.host = j;
     sj.arrival_ns = arrival_ns > 0 ? arrival_ns : mono_ns();
     *ticket = (uint64_t)s->jobs.size();

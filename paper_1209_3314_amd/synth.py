@@ -17,6 +17,10 @@ Recipes (all drawn from ``numpy.random.default_rng``):
      overwritten with v (clipped at the border);
   4. marker = max(mask - offset, 0).
 
+``slide_mr_inputs`` -- reconstruction inputs at whole-slide scale (billions
+of pixels), block-structured so that drawing them takes seconds (see its
+docstring).
+
 ``edt_input`` -- binary nucleus-like image (1 = background to measure,
 0 = feature/target):
   start from all ones; repeatedly draw a shape -- with probability 1/2 a disk
@@ -110,6 +114,32 @@ def edt_input(h: int, w: int, seed: int, coverage: float = 0.30) -> np.ndarray:
             theta = float(rng.uniform(0.0, math.pi))
             zeros += _paint_ellipse(img, cx, cy, a, b, theta, 0)
     return img
+
+
+def slide_mr_inputs(h: int, w: int, seed: int, block: int = 32, offset: int = 40, seed_frac: float = 0.002):
+    """Whole-slide-scale reconstruction inputs that are cheap to draw at
+    billions of pixels: a field of ``block`` x ``block`` blocks with levels
+    uniform in [0, 219], plus a row ripple 4 * (y mod 7) and a column ripple
+    3 * (x mod 5) (so no block is flat); marker = max(mask - offset, 0),
+    except in a ``seed_frac`` fraction of the blocks (drawn after the levels),
+    where marker = mask.  Returns (marker, mask) uint8 arrays of shape (h, w),
+    filled one block row at a time."""
+    rng = np.random.default_rng(seed)
+    bh, bw = (h + block - 1) // block, (w + block - 1) // block
+    levels = rng.integers(0, 220, size=(bh, bw), dtype=np.uint8)
+    seeds = rng.random((bh, bw)) < seed_frac
+    rowr = ((np.arange(h) % 7) * 4).astype(np.uint8)
+    colr = ((np.arange(w) % 5) * 3).astype(np.uint8)
+    mask = np.empty((h, w), dtype=np.uint8)
+    marker = np.empty((h, w), dtype=np.uint8)
+    for by in range(bh):
+        rows = slice(by * block, min((by + 1) * block, h))
+        lv = np.repeat(levels[by], block)[:w]
+        m = lv[None, :] + rowr[rows, None] + colr[None, :]
+        mask[rows] = m
+        sd = np.repeat(seeds[by], block)[:w]
+        marker[rows] = np.where(sd[None, :], m, np.maximum(m.astype(np.int16) - offset, 0).astype(np.uint8))
+    return marker, mask
 
 
 # ---------------------------------------------------------------------------

@@ -92,3 +92,21 @@ def test_graph_rejects_bad_batches(env):
     a = torch.zeros((8, 8), dtype=torch.uint8, device=d)
     with pytest.raises(iw.IwppError):
         ctx.batch_graph([{"op": "recon", "conn": 8, "marker": a, "mask": a, "out": a}])
+
+
+def test_graph_round_times(env):
+    """The graph's own timeline: empty before a replay, one phase per grid
+    barrier of its last persistent kernel after one."""
+    torch, iw, ctx = env
+    jobs, ref = make_jobs(torch, np.random.default_rng(41), 4, sizes=(100, 400))
+    announce("graph round times")
+    g = ctx.batch_graph(jobs)
+    try:
+        assert g.round_times() == []
+        g.launch()
+        torch.cuda.synchronize()
+        check(jobs, ref)
+        rt = g.round_times()
+        assert len(rt) >= 1 and all(t >= 0.0 for t in rt)
+    finally:
+        g.close()

@@ -202,6 +202,42 @@ def test_resident_rejects_host_buffers(env):
         j = _lib.Job(_lib.IWPP_OP_RECON, 8, 16, 16, h.data_ptr(), m.data_ptr(), o.data_ptr(), None)
         import ctypes
         t = ctypes.c_uint64()
-        assert srv._lib.iwpp_server_submit(srv._h, ctypes.byref(j), 0, ctypes.byref(t)) == _lib.IWPP_EINVAL
+        assert srv._lib.iwpp_server_submit(srv._h, ctypes.byref(j), 0, None, ctypes.byref(t)) == _lib.IWPP_EINVAL
     finally:
         srv.stop()
+
+
+def test_resident_job_waits_for_the_callers_stream(env):
+    """Inputs written by kernels still queued on a side stream, and an output
+    buffer that a queued kernel still writes, are submitted with no
+    synchronisation: the job's batch waits for the side stream's work queued
+    before the submit, so the result equals the oracle."""
+    torch, iw, ctx = env
+    d = torch.device("cuda", 0)
+    h, w = 700, 900
+    J, I = synth.mr_inputs(h, w, seed=61, n_disks=60, radius=(3, 12), offset=40)
+    expect = oracle.mr_fh(J, I, 8)
+    hJ, hI = torch.from_numpy(J).pin_memory(), torch.from_numpy(I).pin_memory()
+    side = torch.cuda.Stream(d)
+    srv = iw.Server(ctx, hbm_budget_bytes=256 << 20, resident=True)
+    try:
+        with torch.cuda.stream(side):
+            big = torch.randn((6144, 6144), device=d)
+            marker = torch.zeros((h, w), dtype=torch.uint8, device=d)
+            mask = torch.zeros((h, w), dtype=torch.uint8, device=d)
+            out = torch.empty((h, w), dtype=torch.uint8, device=d)
+            for _ in range(8):  # keep the side stream busy well past the submit
+                big = big @ big
+                big = big / big.abs().max()
+            marker.copy_(hJ, non_blocking=True)
+            mask.copy_(hI, non_blocking=True)
+            out.fill_(9)  # a queued writer of the output buffer
+            announce("serve resident stream order")
+            t = srv.submit({"op": "recon", "conn": 8, "marker": marker, "mask": mask, "out": out}, stream=side)
+        srv.drain(timeout_ms=60000)
+        state, _ = srv.poll(t)
+    finally:
+        srv.stop()
+    assert state == _lib.JOB_DONE
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), expect)
