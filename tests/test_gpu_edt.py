@@ -80,10 +80,20 @@ def test_widest_allowed_row(env):
     check(env, B, 8)
 
 
+def test_first_wide_row(env):
+    """Width 32768: the first size that takes the wide coordinate fields."""
+    B = np.ones((2, 32768), np.uint8)
+    B[0, 0] = 0
+    B[1, 32767] = 0
+    announce("edt 2 x 32768")
+    check(env, B, 8)
+
+
 def test_rejects_oversize(env):
     torch, iw, ctx = env
+    announce("edt oversize")
     with pytest.raises(iw.IwppError):
-        ctx.edt(torch.ones((1, 32768), dtype=torch.uint8, device="cuda"), 8)
+        ctx.edt(torch.ones((1, 46341), dtype=torch.uint8, device="cuda"), 8)
 
 
 @pytest.mark.parametrize("pb", [1, 3, 64])
