@@ -16,12 +16,14 @@
  *   - return value 0 on success, -1 on a bad argument, -2 on allocation failure.
  *
  * Morphological reconstruction (Sec. 2.1):
- *   oracle_mr_fh        sequential Fast Hybrid reconstruction (Algorithm 2).
+ *   oracle_mr_fh        rho_I(J) by a forward pass, a backward pass and a FIFO
+ *                       relaxation (the Fast Hybrid schedule).
  * Euclidean distance transform (Sec. 2.2), targets ("features") are 0-pixels:
  *   oracle_edt_rounds   level-synchronous propagation, frontier form (the
  *                       round reading of Algorithms 3 and 6, see below);
  *   oracle_edt_dense    the same rounds as a dense Jacobi operator;
- *   oracle_edt_alg3     Algorithm 3 taken literally: one FIFO, in place;
+ *   oracle_edt_alg3     the sequential schedule: one FIFO, in place, strict
+ *                       improvement (Algorithm 3's schedule);
  *   oracle_edt_exact_bf exact EDT by brute force over all features;
  *   oracle_edt_exact_sep exact squared EDT, separable lower-envelope method
  *                       (Meijster et al. 2000 / Felzenszwalb-Huttenlocher).
@@ -105,101 +107,129 @@ static int bad_dims(int64_t h, int64_t w, int conn) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Morphological reconstruction by dilation, Fast Hybrid (Sec. 2.1, Alg. 2).
+/* Queue-driven relaxation, shared by both instances.
+ *
+ * The IWPP of Sec. 2 in its plainest form: items wait in a FIFO; popping p
+ * offers p's value to every in-image neighbour q of N_G; an offer that
+ * improves q changes q, and q then waits in the FIFO as well.  What "offer"
+ * and "improve" mean is the instance's business (`offer` returns nonzero when
+ * it changed q).  Counts: pops, pushes, and the largest depth (an item pushed
+ * by an item of depth d has depth d + 1; initial items have depth 0). */
+typedef int (*offer_fn)(void* inst, int64_t p, int64_t q);
+
+typedef struct {
+  int64_t pops, pushes, maxdep;
+} relax_counts;
+
+static int relax_fifo(fifo_t* fq, int64_t h, int64_t w, int conn, offer_fn offer, void* inst, relax_counts* c) {
+  const int nn = nb_count(conn);
+  const int (*nb)[2] = nb_table(conn);
+  while (fq->count > 0) {
+    int64_t p, d;
+    fifo_pop(fq, &p, &d);
+    c->pops++;
+    if (d > c->maxdep) c->maxdep = d;
+    const int64_t y = p / w, x = p % w;
+    for (int k = 0; k < nn; ++k) {
+      const int64_t qy = y + nb[k][0], qx = x + nb[k][1];
+      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
+      const int64_t q = qy * w + qx;
+      if (!offer(inst, p, q)) continue;
+      if (fifo_push(fq, q, d + 1)) return -2;
+      c->pushes++;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Morphological reconstruction by dilation (Sec. 2.1).
+ *
+ * rho_I(J) is the limit of the elementary geodesic dilation
+ *   J(p) <- max{J(q) : q in N_G(p) U {p}} ^ I(p)
+ * and is unique: any order of elementary updates that reaches stability gives
+ * it.  The order used here is the Fast Hybrid schedule the paper builds on:
+ * one forward pass and one backward pass of the update restricted to the half
+ * neighbourhoods (N+ for the forward pass, N- for the backward one), the
+ * backward pass also collecting the pixels whose value can still travel to a
+ * neighbour, then the queue relaxation above until nothing changes.
  *
  * Reading for a marker above the mask: the paper requires J <= I and is silent
- * otherwise; the marker is clamped first (J <- J ^ I), which is what the first
- * raster scan of Algorithm 2 does to every pixel anyway.
+ * otherwise; the marker is clamped first (J <- J ^ I).
  *
  * stats (may be NULL), 4 entries:
- *   [0] pixels queued by the anti-raster scan (initial wavefront)
- *   [1] queue pops in the propagation phase (the work count Q_ref)
- *   [2] queue pushes in the propagation phase
- *   [3] largest BFS depth reached (initial items have depth 0)
+ *   [0] pixels queued by the backward pass (initial wavefront)
+ *   [1] queue pops in the relaxation (the work count Q_ref)
+ *   [2] queue pushes in the relaxation
+ *   [3] largest depth reached (initial items have depth 0)
  */
+typedef struct {
+  uint8_t* J;
+  const uint8_t* I;
+} mr_inst;
+
+/* p's value can raise q: J(q) < J(p) and q is below its mask. */
+static int mr_can_raise(const mr_inst* m, int64_t p, int64_t q) { return m->J[q] < m->J[p] && m->J[q] < m->I[q]; }
+
+static int mr_offer(void* inst, int64_t p, int64_t q) {
+  mr_inst* m = (mr_inst*)inst;
+  if (!mr_can_raise(m, p, q)) return 0;
+  m->J[q] = m->J[p] < m->I[q] ? m->J[p] : m->I[q];
+  return 1;
+}
+
+/* One pass of the update restricted to the neighbour offsets nb[k0..k1), in
+ * raster order (backward = 0) or reverse raster order (backward = 1).  With
+ * `seeds`, every pixel that afterwards can raise one of those neighbours is
+ * queued (in visiting order) and counted in *nseeds. */
+static int mr_pass(mr_inst* m, int64_t h, int64_t w, const int (*nb)[2], int k0, int k1, int backward, fifo_t* seeds,
+                   int64_t* nseeds) {
+  const int64_t n = h * w;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t p = backward ? n - 1 - i : i;
+    const int64_t y = p / w, x = p % w;
+    uint8_t v = m->J[p];
+    for (int k = k0; k < k1; ++k) {
+      const int64_t qy = y + nb[k][0], qx = x + nb[k][1];
+      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
+      if (m->J[qy * w + qx] > v) v = m->J[qy * w + qx];
+    }
+    m->J[p] = v < m->I[p] ? v : m->I[p];
+    if (!seeds) continue;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t qy = y + nb[k][0], qx = x + nb[k][1];
+      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
+      if (mr_can_raise(m, p, qy * w + qx)) {
+        if (fifo_push(seeds, p, 0)) return -2;
+        (*nseeds)++;
+        break;
+      }
+    }
+  }
+  return 0;
+}
+
 int oracle_mr_fh(const uint8_t* marker, const uint8_t* mask, uint8_t* out, int64_t h, int64_t w, int conn,
                  int64_t* stats) {
   if (!marker || !mask || !out || bad_dims(h, w, conn)) return -1;
   const int64_t n = h * w;
   const int nn = nb_count(conn), half = nn / 2;
-  const int (*nb)[2] = nb_table(conn);
-  uint8_t* J = out;
-  const uint8_t* I = mask;
-  for (int64_t p = 0; p < n; ++p) J[p] = marker[p] < mask[p] ? marker[p] : mask[p];
-
-  /* Raster scan: J(p) <- max{J(q), q in N+(p) U {p}} ^ I(p). */
-  for (int64_t y = 0; y < h; ++y)
-    for (int64_t x = 0; x < w; ++x) {
-      int64_t p = y * w + x;
-      uint8_t m = J[p];
-      for (int k = 0; k < half; ++k) {
-        int64_t qy = y + nb[k][0], qx = x + nb[k][1];
-        if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
-        if (J[qy * w + qx] > m) m = J[qy * w + qx];
-      }
-      J[p] = m < I[p] ? m : I[p];
-    }
-
+  mr_inst m = {out, mask};
+  for (int64_t p = 0; p < n; ++p) out[p] = marker[p] < mask[p] ? marker[p] : mask[p];
   fifo_t fq;
-  if (fifo_init(&fq, n / 4 + 16)) {
-    fifo_free(&fq);
-    return -2;
-  }
-  int64_t initial = 0, pops = 0, pushes = 0, maxdep = 0;
-
-  /* Anti-raster scan with N-; queue p when some q in N-(p) can still be raised by p. */
-  for (int64_t y = h - 1; y >= 0; --y)
-    for (int64_t x = w - 1; x >= 0; --x) {
-      int64_t p = y * w + x;
-      uint8_t m = J[p];
-      for (int k = half; k < nn; ++k) {
-        int64_t qy = y + nb[k][0], qx = x + nb[k][1];
-        if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
-        if (J[qy * w + qx] > m) m = J[qy * w + qx];
-      }
-      J[p] = m < I[p] ? m : I[p];
-      for (int k = half; k < nn; ++k) {
-        int64_t qy = y + nb[k][0], qx = x + nb[k][1];
-        if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
-        int64_t q = qy * w + qx;
-        if (J[q] < J[p] && J[q] < I[q]) {
-          if (fifo_push(&fq, p, 0)) {
-            fifo_free(&fq);
-            return -2;
-          }
-          initial++;
-          break;
-        }
-      }
-    }
-
-  /* Wavefront propagation phase: FIFO until empty. */
-  while (fq.count > 0) {
-    int64_t p, d;
-    fifo_pop(&fq, &p, &d);
-    pops++;
-    if (d > maxdep) maxdep = d;
-    int64_t y = p / w, x = p % w;
-    for (int k = 0; k < nn; ++k) {
-      int64_t qy = y + nb[k][0], qx = x + nb[k][1];
-      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
-      int64_t q = qy * w + qx;
-      if (J[q] < J[p] && I[q] != J[q]) {
-        J[q] = J[p] < I[q] ? J[p] : I[q];
-        if (fifo_push(&fq, q, d + 1)) {
-          fifo_free(&fq);
-          return -2;
-        }
-        pushes++;
-      }
-    }
-  }
+  int rc = fifo_init(&fq, n / 4 + 16);
+  int64_t initial = 0;
+  relax_counts c = {0, 0, 0};
+  if (!rc) rc = mr_pass(&m, h, w, nb_table(conn), 0, half, 0, NULL, NULL);       /* N+ (offsets before p) */
+  if (!rc) rc = mr_pass(&m, h, w, nb_table(conn), half, nn, 1, &fq, &initial);   /* N- (offsets after p) */
+  if (!rc) rc = relax_fifo(&fq, h, w, conn, mr_offer, &m, &c);
   fifo_free(&fq);
+  if (rc) return rc;
   if (stats) {
     stats[0] = initial;
-    stats[1] = pops;
-    stats[2] = pushes;
-    stats[3] = maxdep;
+    stats[1] = c.pops;
+    stats[2] = c.pushes;
+    stats[3] = c.maxdep;
   }
   return 0;
 }
@@ -406,57 +436,51 @@ done:
   return rc;
 }
 
-/* Algorithm 3 taken literally: VR(p) = p for features, inf otherwise; the
- * contour features are queued in raster order; a FIFO pops p and, for each
- * in-image neighbour q in the order of N_G above, copies VR(p) into VR(q) when
- * DIST(q, VR(p)) < DIST(q, VR(q)) (strict, no tie-break) and queues q; the
- * update is in place, so later offers see earlier ones.
+/* The sequential propagation EDT of Sec. 2.2 (the schedule of Algorithm 3),
+ * used to measure how far the round semantics are from it: every pixel holds
+ * a nearest-feature candidate VR (itself for a feature, none otherwise); the
+ * contour features wait in the FIFO in raster order; the queue relaxation
+ * above offers VR(p) to each neighbour q, which takes it when it is strictly
+ * closer than q's own candidate (no tie-break), in place, so later offers see
+ * earlier ones.
  * stats (may be NULL), 1 entry: [0] queue pops. */
+typedef struct {
+  int64_t* vr;
+  int64_t w;
+} edt_seq_inst;
+
+static int edt_seq_offer(void* inst, int64_t p, int64_t q) {
+  edt_seq_inst* e = (edt_seq_inst*)inst;
+  const int64_t w = e->w, s = e->vr[p];
+  const int64_t qy = q / w, qx = q % w;
+  const int64_t cur = e->vr[q] < 0 ? ORACLE_INF64 : sqd(qy, qx, e->vr[q] / w, e->vr[q] % w);
+  if (sqd(qy, qx, s / w, s % w) >= cur) return 0;
+  e->vr[q] = s;
+  return 1;
+}
+
 int oracle_edt_alg3(const uint8_t* bin, int32_t* sqdist, int32_t* nearest, int64_t h, int64_t w, int conn,
                     int64_t* stats) {
   if (!bin || !sqdist || !nearest || bad_dims(h, w, conn)) return -1;
   const int64_t n = h * w;
-  const int nn = nb_count(conn);
-  const int (*nb)[2] = nb_table(conn);
   int64_t* vr = (int64_t*)malloc((size_t)n * sizeof(int64_t));
   int64_t* d2 = (int64_t*)malloc((size_t)n * sizeof(int64_t));
   fifo_t fq;
   int rc = fifo_init(&fq, n / 4 + 16);
+  relax_counts c = {0, 0, 0};
   if (!vr || !d2 || rc) {
     rc = -2;
     goto done;
   }
   for (int64_t p = 0; p < n; ++p) vr[p] = bin[p] == 0 ? p : -1;
-  for (int64_t y = 0; y < h; ++y)
-    for (int64_t x = 0; x < w; ++x)
-      if (is_contour(bin, h, w, y, x, conn) && fifo_push(&fq, y * w + x, 0)) {
-        rc = -2;
-        goto done;
-      }
-  int64_t pops = 0;
-  while (fq.count > 0) {
-    int64_t p, d;
-    fifo_pop(&fq, &p, &d);
-    pops++;
-    int64_t py = p / w, px = p % w, s = vr[p];
-    int64_t sy = s / w, sx = s % w;
-    for (int k = 0; k < nn; ++k) {
-      int64_t qy = py + nb[k][0], qx = px + nb[k][1];
-      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
-      int64_t q = qy * w + qx;
-      int64_t cur = vr[q] < 0 ? ORACLE_INF64 : sqd(qy, qx, vr[q] / w, vr[q] % w);
-      if (sqd(qy, qx, sy, sx) < cur) {
-        vr[q] = s;
-        if (fifo_push(&fq, q, d + 1)) {
-          rc = -2;
-          goto done;
-        }
-      }
-    }
-  }
+  for (int64_t p = 0; p < n && !rc; ++p)
+    if (is_contour(bin, h, w, p / w, p % w, conn)) rc = fifo_push(&fq, p, 0);
+  edt_seq_inst e = {vr, w};
+  if (!rc) rc = relax_fifo(&fq, h, w, conn, edt_seq_offer, &e, &c);
+  if (rc) goto done;
   for (int64_t p = 0; p < n; ++p) d2[p] = vr[p] < 0 ? ORACLE_INF64 : sqd(p / w, p % w, vr[p] / w, vr[p] % w);
   edt_write(vr, d2, sqdist, nearest, n);
-  if (stats) stats[0] = pops;
+  if (stats) stats[0] = c.pops;
 done:
   fifo_free(&fq);
   free(vr);
