@@ -153,6 +153,35 @@ const char* iwpp_last_error(const iwpp_ctx* ctx);
 int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
                             int32_t height, int32_t width, int32_t conn, void* stream);
 
+/* Bytes of the static device work area of iwpp_morph_recon_u8_noalloc (one
+ * per device, held until the process ends). */
+#define IWPP_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* iwpp_morph_recon_u8 for callers that cannot allocate device memory during a
+ * call: code under HIP stream/graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, rules and result bytes as
+ * iwpp_morph_recon_u8, but the work lists, flags, counters and grid barrier
+ * live in a static device array of IWPP_NOALLOC_SCRATCH_BYTES instead of the
+ * context's growable scratch; the call performs no hipMalloc, hipFree or
+ * event creation (the context's profile recording does not apply to it).
+ * The array's device address is looked up once per device by iwpp_create.
+ *
+ * Limit: the image's tile scratch (about 336 bytes per 64x64 tile) must fit
+ * the area, i.e. at most about 99,800 tiles -- e.g. 16384 x 24576
+ * (98,304 tiles) fits, 20480 x 20480 (102,400 tiles) does not; a larger image
+ * returns IWPP_EINVAL with the sizes in iwpp_last_error.
+ *
+ * Sharing: every call on a device uses that device's one array, which keeps
+ * the last call's contents (counters are cleared at the start of each call).
+ * Calls that overlap on one device -- from any context, on any stream -- race
+ * and give wrong results: order them (one stream, or events).  iwpp_get_stats
+ * and iwpp_round_times on the context read the last such call's counters
+ * until another call on the device replaces them.
+ * Errors: as iwpp_morph_recon_u8, plus IWPP_EINVAL for an image above the
+ * limit and IWPP_EDEVICE if the area could not be set up. */
+int32_t iwpp_morph_recon_u8_noalloc(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
+                                    int32_t height, int32_t width, int32_t conn, void* stream);
+
 /* Euclidean distance transform by propagation of the nearest feature
  * (Sec. 2.2, Algorithms 3 and 6).  Features (the paper's background, the
  * targets of the distance) are the 0-pixels of `binary`; every pixel receives

@@ -121,6 +121,26 @@ class Context:
             self._err(rc)
         return out
 
+    def morph_recon_noalloc(self, marker, mask, out, conn: int = 8):
+        """morph_recon through iwpp_morph_recon_u8_noalloc: no device memory is
+        allocated, neither by the library (its work area is a static device
+        array) nor here (`out` is required).  Calls on one device must not
+        overlap."""
+        torch = _torch()
+        _check_image(mask, "mask", torch.uint8)
+        _check_image(marker, "marker", torch.uint8, mask.device)
+        _check_image(out, "out", torch.uint8, mask.device)
+        if marker.shape != mask.shape or out.shape != mask.shape:
+            raise ValueError("marker, mask and out must have the same shape")
+        if conn not in (4, 8):
+            raise ValueError("conn must be 4 or 8")
+        h, w = mask.shape
+        rc = self._lib.iwpp_morph_recon_u8_noalloc(self._h, marker.data_ptr(), mask.data_ptr(), out.data_ptr(),
+                                                   h, w, conn, self._stream(mask.device))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return out
+
     def edt(self, binary, conn: int = 8, out=None):
         torch = _torch()
         _check_image(binary, "binary", torch.uint8)

@@ -21,7 +21,10 @@ EXPORTED = (
     "iwpp_server_get_stats", "iwpp_server_stop", "iwpp_batch_graph_create", "iwpp_batch_graph_launch", "iwpp_batch_graph_stats", "iwpp_batch_graph_destroy",
     "iwpp_batch_graph_round_times",
     "iwpp_round_work",
+    "iwpp_morph_recon_u8_noalloc",
 )
+# Size of the static work area of iwpp_morph_recon_u8_noalloc (IWPP_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 32 << 20
 IWPP_OP_RECON = 1
 IWPP_OP_EDT = 2
 
@@ -115,6 +118,8 @@ def load():
     lib.iwpp_last_error.restype = ctypes.c_char_p
     lib.iwpp_morph_recon_u8.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
     lib.iwpp_morph_recon_u8.restype = i32
+    lib.iwpp_morph_recon_u8_noalloc.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
+    lib.iwpp_morph_recon_u8_noalloc.restype = i32
     lib.iwpp_edt.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
     lib.iwpp_edt.restype = i32
     lib.iwpp_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]

@@ -476,6 +476,9 @@ int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out) {
     g_create_err = "iwpp_create: device memset failed";
     return IWPP_EDEVICE;
   }
+  // Set-up of the allocation-free entry point; if it fails that entry point
+  // reports IWPP_EDEVICE and everything else works.
+  (void)noalloc_setup(ctx);
   *out = ctx;
   return IWPP_OK;
 }

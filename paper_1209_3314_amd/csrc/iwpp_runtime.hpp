@@ -86,6 +86,7 @@ struct iwpp_ctx {
   int last_op = 0;
   bool have_call = false;
   iwpp_server* server = nullptr;  // a running server owns the context
+  uint8_t* noalloc = nullptr;     // device address of the static work area on this device (null: unavailable)
   iwpp::Recorder rec;
 };
 
@@ -105,5 +106,10 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
 // Sum the sharded statistics words copied from a fixed area.
 // (The round timeline is read by iwpp_round_times.)
 void fold_stats(const unsigned long long* shards, int op, iwpp_stats* out);
+// Look up the static work area of iwpp_morph_recon_u8_noalloc on the context's
+// device (which must be current) once per device and store it in ctx->noalloc.
+int32_t noalloc_setup(iwpp_ctx* ctx);
+// Bytes of the static area left for a group's scratch after its fixed area.
+size_t noalloc_group_limit();
 
 }  // namespace iwpp::rt
