@@ -54,6 +54,7 @@ def _load():
     i64p = ctypes.POINTER(ctypes.c_int64)
     i64 = ctypes.c_int64
     lib.oracle_mr_fh.argtypes = [u8p, u8p, u8p, i64, i64, ctypes.c_int, i64p]
+    lib.oracle_mr_erode.argtypes = [u8p, u8p, u8p, i64, i64, ctypes.c_int, i64p]
     for name in ("oracle_edt_rounds", "oracle_edt_dense", "oracle_edt_alg3"):
         getattr(lib, name).argtypes = [u8p, i32p, i32p, i64, i64, ctypes.c_int, i64p]
     lib.oracle_edt_exact_bf.argtypes = [u8p, i32p, i32p, i64, i64]
@@ -104,6 +105,52 @@ def mr_fh(marker, mask, conn: int = 8, return_stats: bool = False):
     if return_stats:
         return out, {"initial": int(st[0]), "pops": int(st[1]), "pushes": int(st[2]), "depth": int(st[3])}
     return out
+
+
+def mr_erode(marker, mask, conn: int = 8, return_stats: bool = False):
+    """Reconstruction by erosion rho*_I(J): the limit of
+    J(p) <- max(min{J(q) : q in N_G(p) U {p}}, I(p)) from a marker above the
+    mask (a marker below the mask is raised to it first).  Stats as mr_fh."""
+    lib = _load()
+    J, I = _u8(marker), _u8(mask)
+    if J.shape != I.shape:
+        raise ValueError("marker and mask must have the same shape")
+    h, w = J.shape
+    out = np.empty_like(J)
+    st = np.zeros(4, dtype=np.int64)
+    _check(lib.oracle_mr_erode(_ptr(J, ctypes.c_uint8), _ptr(I, ctypes.c_uint8), _ptr(out, ctypes.c_uint8),
+                               h, w, conn, _ptr(st, ctypes.c_int64)), "oracle_mr_erode")
+    if return_stats:
+        return out, {"initial": int(st[0]), "pops": int(st[1]), "pushes": int(st[2]), "depth": int(st[3])}
+    return out
+
+
+def geodesic_erosion(J: np.ndarray, I: np.ndarray, conn: int = 8) -> np.ndarray:
+    """One elementary geodesic erosion: J'(p) = max(min{J(q) : q in N_G(p) U {p}}, I(p));
+    pixels outside the image are not neighbours."""
+    J = np.asarray(J)
+    h, w = J.shape
+    P = np.full((h + 2, w + 2), 256, dtype=np.int16)  # 256 padding never wins a min of bytes
+    P[1:-1, 1:-1] = J
+    m = P[1:-1, 1:-1].copy()
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if (dy, dx) == (0, 0) or (conn == 4 and dy != 0 and dx != 0):
+                continue
+            m = np.minimum(m, P[1 + dy:h + 1 + dy, 1 + dx:w + 1 + dx])
+    return np.maximum(m, np.asarray(I)).astype(np.uint8)
+
+
+def mr_erode_iterate(marker, mask, conn: int = 8) -> np.ndarray:
+    """rho*_I(J) by its definition: geodesic erosions from max(J, I) until
+    nothing changes (slow; small images)."""
+    I = _u8(mask)
+    J = np.maximum(_u8(marker), I)
+    while True:
+        K = geodesic_erosion(J, I, conn)
+        if np.array_equal(K, J):
+            return J
+        J = K
 
 
 def geodesic_dilation(J: np.ndarray, I: np.ndarray, conn: int = 8) -> np.ndarray:

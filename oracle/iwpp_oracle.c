@@ -17,7 +17,9 @@
  *
  * Morphological reconstruction (Sec. 2.1):
  *   oracle_mr_fh        rho_I(J) by a forward pass, a backward pass and a FIFO
- *                       relaxation (the Fast Hybrid schedule).
+ *                       relaxation (the Fast Hybrid schedule);
+ *   oracle_mr_erode     the dual, reconstruction by erosion rho*_I(J), on the
+ *                       same schedule with the comparisons reversed.
  * Euclidean distance transform (Sec. 2.2), targets ("features") are 0-pixels:
  *   oracle_edt_rounds   level-synchronous propagation, frontier form (the
  *                       round reading of Algorithms 3 and 6, see below);
@@ -223,6 +225,77 @@ int oracle_mr_fh(const uint8_t* marker, const uint8_t* mask, uint8_t* out, int64
   if (!rc) rc = mr_pass(&m, h, w, nb_table(conn), 0, half, 0, NULL, NULL);       /* N+ (offsets before p) */
   if (!rc) rc = mr_pass(&m, h, w, nb_table(conn), half, nn, 1, &fq, &initial);   /* N- (offsets after p) */
   if (!rc) rc = relax_fifo(&fq, h, w, conn, mr_offer, &m, &c);
+  fifo_free(&fq);
+  if (rc) return rc;
+  if (stats) {
+    stats[0] = initial;
+    stats[1] = c.pops;
+    stats[2] = c.pushes;
+    stats[3] = c.maxdep;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Morphological reconstruction by erosion (the dual instance, Sec. 1 lists it
+ * among the IWPP users): rho*_I(J) is the limit of the elementary geodesic
+ * erosion
+ *   J(p) <- max(min{J(q) : q in N_G(p) U {p}}, I(p))
+ * from a marker above the mask, and is unique like rho_I(J).  Same schedule
+ * as oracle_mr_fh with every comparison reversed: a forward pass over N+, a
+ * backward pass over N- that queues the pixels whose value can still travel
+ * down to a neighbour, then the FIFO relaxation.  A marker below the mask is
+ * raised to it first (J <- J v I).  stats: as oracle_mr_fh. */
+static int mr_can_lower(const mr_inst* m, int64_t p, int64_t q) { return m->J[q] > m->J[p] && m->J[q] > m->I[q]; }
+
+static int mr_erode_offer(void* inst, int64_t p, int64_t q) {
+  mr_inst* m = (mr_inst*)inst;
+  if (!mr_can_lower(m, p, q)) return 0;
+  m->J[q] = m->J[p] > m->I[q] ? m->J[p] : m->I[q];
+  return 1;
+}
+
+static int mr_erode_pass(mr_inst* m, int64_t h, int64_t w, const int (*nb)[2], int k0, int k1, int backward,
+                         fifo_t* seeds, int64_t* nseeds) {
+  const int64_t n = h * w;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t p = backward ? n - 1 - i : i;
+    const int64_t y = p / w, x = p % w;
+    uint8_t v = m->J[p];
+    for (int k = k0; k < k1; ++k) {
+      const int64_t qy = y + nb[k][0], qx = x + nb[k][1];
+      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
+      if (m->J[qy * w + qx] < v) v = m->J[qy * w + qx];
+    }
+    m->J[p] = v > m->I[p] ? v : m->I[p];
+    if (!seeds) continue;
+    for (int k = k0; k < k1; ++k) {
+      const int64_t qy = y + nb[k][0], qx = x + nb[k][1];
+      if (qy < 0 || qy >= h || qx < 0 || qx >= w) continue;
+      if (mr_can_lower(m, p, qy * w + qx)) {
+        if (fifo_push(seeds, p, 0)) return -2;
+        (*nseeds)++;
+        break;
+      }
+    }
+  }
+  return 0;
+}
+
+int oracle_mr_erode(const uint8_t* marker, const uint8_t* mask, uint8_t* out, int64_t h, int64_t w, int conn,
+                    int64_t* stats) {
+  if (!marker || !mask || !out || bad_dims(h, w, conn)) return -1;
+  const int64_t n = h * w;
+  const int nn = nb_count(conn), half = nn / 2;
+  mr_inst m = {out, mask};
+  for (int64_t p = 0; p < n; ++p) out[p] = marker[p] > mask[p] ? marker[p] : mask[p];
+  fifo_t fq;
+  int rc = fifo_init(&fq, n / 4 + 16);
+  int64_t initial = 0;
+  relax_counts c = {0, 0, 0};
+  if (!rc) rc = mr_erode_pass(&m, h, w, nb_table(conn), 0, half, 0, NULL, NULL);
+  if (!rc) rc = mr_erode_pass(&m, h, w, nb_table(conn), half, nn, 1, &fq, &initial);
+  if (!rc) rc = relax_fifo(&fq, h, w, conn, mr_erode_offer, &m, &c);
   fifo_free(&fq);
   if (rc) return rc;
   if (stats) {

@@ -167,3 +167,62 @@ def test_scans_do_monotone_work(conn):
         R, stt = oracle.mr_fh(J, I, conn, return_stats=True)
         assert (R == 200).all()
         assert stt["initial"] == 0 and stt["pops"] == 0
+
+
+# ---- reconstruction by erosion (the dual instance) -----------------------------
+
+def threshold_reconstruction_erode(J, I, conn):
+    """rho*_I(J)(p) = min{t : p lies in a connected component of {I <= t}
+    that meets {J v I <= t}} -- erosion-reconstruction as a stack of binary
+    reconstructions of the lower level sets, with scipy's labelling."""
+    Jc = np.maximum(J, I)
+    struct = ndimage.generate_binary_structure(2, 2 if conn == 8 else 1)
+    R = np.full(I.shape, 255, np.int32)
+    for t in range(254, int(I.min()) - 1, -1):
+        lab, _ = ndimage.label(I <= t, structure=struct)
+        hit = np.unique(lab[(Jc <= t) & (lab > 0)])
+        R -= np.isin(lab, hit[hit > 0])
+    return R.astype(np.uint8)
+
+
+@settings(max_examples=120, deadline=None)
+@given(images, st.sampled_from([4, 8]))
+def test_erode_equals_its_definition(spec, conn):
+    h, w, levels, seed = spec
+    J, I = random_pair(np.random.default_rng(seed), h, w, levels)
+    assert np.array_equal(oracle.mr_erode(J, I, conn), oracle.mr_erode_iterate(J, I, conn))
+
+
+@settings(max_examples=40, deadline=None)
+@given(images, st.sampled_from([4, 8]))
+def test_erode_definition_equals_threshold_decomposition(spec, conn):
+    h, w, levels, seed = spec
+    rng = np.random.default_rng(seed)
+    J, I = random_pair(rng, h, w, min(levels, 16))
+    J, I = (255 - J).astype(np.uint8), (255 - I).astype(np.uint8)  # levels near the top of the range
+    assert np.array_equal(oracle.mr_erode_iterate(J, I, conn), threshold_reconstruction_erode(J, I, conn))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_erode_is_the_dual_of_dilate(conn):
+    """rho*_I(J) = 255 - rho_{255-I}(255-J) (complementing swaps the order)."""
+    rng = np.random.default_rng(21)
+    for _ in range(5):
+        J, I = random_pair(rng, 37, 41, 256)
+        got = oracle.mr_erode(J, I, conn)
+        assert np.array_equal(got, 255 - oracle.mr_fh(255 - J, 255 - I, conn))
+    J, I = synth.workload_mr_small()
+    Jd = np.minimum(I.astype(np.int16) + 32, 255).astype(np.uint8)  # a marker above the mask
+    assert np.array_equal(oracle.mr_erode(Jd, I, conn), 255 - oracle.mr_fh(255 - Jd, 255 - I, conn))
+
+
+@pytest.mark.parametrize("conn", [4, 8])
+def test_erode_invariants(conn):
+    rng = np.random.default_rng(12)
+    J, I = random_pair(rng, 33, 29, 256)
+    R = oracle.mr_erode(J, I, conn)
+    assert (I <= R).all() and (R <= np.maximum(J, I)).all()
+    assert np.array_equal(oracle.mr_erode(R, I, conn), R)  # idempotent
+    assert np.array_equal(oracle.geodesic_erosion(R, I, conn), R)  # stable under one more erosion
+    assert np.array_equal(oracle.mr_erode(I, I, conn), I)  # marker = mask
+    assert np.array_equal(oracle.mr_erode(np.full_like(I, 255), I, conn), np.full_like(I, 255))  # nothing to descend from
