@@ -6,7 +6,8 @@
  * Hybrid CPU-GPU Machines" (arXiv 1209.3314):
  *
  *   - grayscale morphological reconstruction by dilation, rho_I(J)
- *     (Sec. 2.1 and Algorithms 2 and 5), 4- or 8-connected;
+ *     (Sec. 2.1 and Algorithms 2 and 5), 4- or 8-connected, and its dual,
+ *     reconstruction by erosion (one of the pattern's other users, Sec. 1);
  *   - the propagation-based Euclidean distance transform that carries the
  *     nearest feature of every pixel (Sec. 2.2 and Algorithms 3 and 6).
  *
@@ -76,7 +77,17 @@ typedef struct {
    * paper varies the number of initial scans in Table 1; 0 = 1 with
    * 8-connectivity, 2 with 4-connectivity). */
   int32_t mr_seed_sweeps;
-  int32_t reserved[6];
+  /* Waves per workgroup of the persistent kernels, 4 or 8 (0 = 4): the
+   * workgroup size (the paper's threads per block; a wave holds one tile). */
+  int32_t wg_waves;
+  /* Work-list items a wave stages in LDS before one global atomic appends
+   * them (the depth of the paper's per-block queue): 1 .. 64 (0 = 64). */
+  int32_t stage_depth;
+  /* Reconstruction seed pass: tiles of 64 x 64 per vertical strip that a
+   * wave sweeps top to bottom, each tile reading the one above it fresh (the
+   * seed pass's tiling; 0 = automatic). */
+  int32_t mr_seed_strip;
+  int32_t reserved[3];
 } iwpp_options;
 
 /* Counters of the last compute call on a context (see iwpp_get_stats). */
@@ -105,7 +116,10 @@ enum {
   IWPP_K_MR_DETECT = 2,    /* reserved (no separate seed detection) */
   IWPP_K_MR_PROPAGATE = 3, /* reconstruction: persistent kernel, seed pass + propagation */
   IWPP_K_EDT_INIT = 4,     /* distance transform initialisation */
-  IWPP_K_EDT_ROUNDS = 5    /* distance transform rounds + finalisation */
+  IWPP_K_EDT_ROUNDS = 5,   /* distance transform rounds + finalisation */
+  IWPP_K_MRQ_INIT = 6,     /* pixel-queue reconstruction: working copy + initial queue */
+  IWPP_K_MRQ_PROPAGATE = 7, /* pixel-queue reconstruction: queue rounds */
+  IWPP_K_XEDT = 8            /* exact EDT: column and row passes together */
 };
 
 /* Library version, (major << 16) | minor. */
@@ -182,6 +196,54 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
 int32_t iwpp_morph_recon_u8_noalloc(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
                                     int32_t height, int32_t width, int32_t conn, void* stream);
 
+/* Grayscale morphological reconstruction by erosion of mask I from marker J,
+ * rho*_I(J): the limit of J(p) <- max(min{J(q) : q in N_G(p) U {p}}, I(p))
+ * applied until nothing changes -- the dual of reconstruction by dilation and
+ * another instance of the pattern (Sec. 1).  Computed by the reconstruction
+ * kernels on complemented bytes (rho*_I(J) = 255 - rho_{255-I}(255-J)): each
+ * image byte is complemented as it is loaded and as the result is stored, so
+ * the arguments, layout, limits and errors are those of iwpp_morph_recon_u8.
+ * A marker below the mask is raised to it first (the result is
+ * rho*_I(max(J, I))).  In batches its op is IWPP_OP_RECON_ERODE; it shares
+ * the launches of the 4- or 8-connected dilation group. */
+int32_t iwpp_morph_recon_erode_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
+                                  int32_t height, int32_t width, int32_t conn, void* stream);
+
+/* How the pixel-queue reconstruction appends to a round's queue. */
+enum {
+  IWPP_QUEUE_NAIVE = 0,  /* one global atomic per appended item */
+  IWPP_QUEUE_BALLOT = 1, /* one global atomic per wave and append step (ballot + mbcnt offsets) */
+  IWPP_QUEUE_STAGED = 2  /* items staged per wave in LDS, one global atomic per flush */
+};
+
+typedef struct {
+  int32_t append_mode; /* IWPP_QUEUE_* */
+  int32_t seed_sweeps; /* sweep iterations per tile of the seed pass (0 = as iwpp_morph_recon_u8) */
+  int64_t capacity;    /* items per round queue; appends past it are dropped and recovered (0 = 2*h*w + 64) */
+  int32_t reserved[4];
+} iwpp_queue_options;
+
+/* Reconstruction by dilation with the paper's pixel queue (Algorithm 5's
+ * propagation, Sec. 3.2), kept to compare with the tile design of
+ * iwpp_morph_recon_u8 (same result, bit for bit; it is slower).  After the
+ * same tile seed pass (`seed_sweeps` iterations: the analogue of the number
+ * of initial scans of Table 1), every pixel with a neighbour it can raise is
+ * queued; rounds then pop one item per lane, raise each neighbour q with
+ * J(q) < J(p) and J(q) < I(q) by an atomic maximum on a 32-bit working copy,
+ * and queue q when that atomic raised it.  `append_mode` selects how items
+ * enter a round's queue.  A queue that reaches `capacity` drops, flags, and
+ * once the queues drain is rebuilt from the current image by dense seed
+ * detection (the restart of Sec. 3.2 / Sec. 5.2.4; counted in
+ * iwpp_stats.overflow_restarts).  iwpp_get_stats: seeds = initial queue,
+ * items = pops, updates = successful atomic raises, rounds = queue rounds.
+ * Scratch: 4 bytes per pixel plus 8 bytes per capacity item.
+ *   arguments as iwpp_morph_recon_u8; at most 2^31 - 1 pixels; qopt may be
+ *   NULL (staged appends, default capacity).
+ * Errors: as iwpp_morph_recon_u8, plus IWPP_EINVAL for bad queue options. */
+int32_t iwpp_morph_recon_queue_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
+                                  int32_t height, int32_t width, int32_t conn, const iwpp_queue_options* qopt,
+                                  void* stream);
+
 /* Euclidean distance transform by propagation of the nearest feature
  * (Sec. 2.2, Algorithms 3 and 6).  Features (the paper's background, the
  * targets of the distance) are the 0-pixels of `binary`; every pixel receives
@@ -209,19 +271,35 @@ int32_t iwpp_morph_recon_u8_noalloc(iwpp_ctx* ctx, const uint8_t* marker, const 
 int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
                  int32_t width, int32_t conn, void* stream);
 
+/* The exact Euclidean distance transform.  The propagation of iwpp_edt is an
+ * approximation (Sec. 2.2: the 8-neighbour propagation misses some nearest
+ * features; exact distances need further processing).  This call computes the
+ * exact transform by the separable method of Meijster, Roerdink and
+ * Hesselink (2000): per column the nearest feature in the column, then per
+ * row the lower envelope of the parabolas (x - x')^2 + dy(x')^2, in integer
+ * arithmetic.  sqdist is the exact squared distance to the nearest feature;
+ * nearest is y*width + x of a feature at exactly that distance (of several,
+ * the one in the smallest column, then the smallest row).  No counters
+ * (iwpp_get_stats reports zeros).  Scratch: about 16 bytes per pixel.
+ *   binary, sqdist, nearest, height, width : as iwpp_edt (no connectivity)
+ * If the image has no feature, sqdist and nearest are -1 everywhere.
+ * Errors: as iwpp_edt. */
+int32_t iwpp_edt_exact(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
+                       int32_t width, void* stream);
+
 /* One image of a batch (see iwpp_run_batch). */
 typedef struct {
-  int32_t op;          /* IWPP_OP_RECON or IWPP_OP_EDT */
+  int32_t op;          /* IWPP_OP_RECON, IWPP_OP_RECON_ERODE or IWPP_OP_EDT */
   int32_t conn;        /* 4 or 8 */
   int32_t height;
   int32_t width;
-  const uint8_t* in0;  /* recon: marker; EDT: binary (0 = feature) */
-  const uint8_t* in1;  /* recon: mask; EDT: NULL */
-  void* out0;          /* recon: uint8 result (may equal in0); EDT: int32 sqdist */
+  const uint8_t* in0;  /* recon (either): marker; EDT: binary (0 = feature) */
+  const uint8_t* in1;  /* recon (either): mask; EDT: NULL */
+  void* out0;          /* recon (either): uint8 result (may equal in0); EDT: int32 sqdist */
   void* out1;          /* recon: NULL; EDT: int32 nearest */
 } iwpp_job;
 
-enum { IWPP_OP_RECON = 1, IWPP_OP_EDT = 2 };
+enum { IWPP_OP_RECON = 1, IWPP_OP_EDT = 2, IWPP_OP_RECON_ERODE = 3 };
 
 /* Process many images of mixed sizes and both operations with few launches:
  * jobs are grouped by (op, conn) and every group runs as one seed pass and

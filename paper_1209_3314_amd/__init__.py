@@ -8,6 +8,7 @@ the stream; every step of the computation runs in the library's HIP kernels.
 There is no CPU fallback: the calls raise if the library or a GPU is missing.
 
     morph_recon(marker, mask, conn=8, out=None) -> uint8 tensor   (Sec. 2.1)
+    morph_recon_erode(marker, mask, conn=8, out=None) -> uint8     (the dual)
     edt(binary, conn=8) -> (sqdist int32, nearest int32)         (Sec. 2.2)
 """
 from __future__ import annotations
@@ -17,7 +18,7 @@ import threading
 
 from . import _lib
 
-__all__ = ["Context", "BatchGraph", "Server", "IwppError", "morph_recon", "edt", "last_stats"]
+__all__ = ["Context", "BatchGraph", "Server", "IwppError", "morph_recon", "morph_recon_erode", "edt", "last_stats"]
 
 
 class IwppError(RuntimeError):
@@ -55,10 +56,12 @@ class Context:
     context per device and the current torch stream."""
 
     def __init__(self, device: int = 0, mr_list_capacity: int = 0, mr_max_sweeps: int = 0,
-                 persistent_blocks: int = 0, profile: bool = False, mr_seed_sweeps: int = 0):
+                 persistent_blocks: int = 0, profile: bool = False, mr_seed_sweeps: int = 0, wg_waves: int = 0,
+                 stage_depth: int = 0, mr_seed_strip: int = 0):
         lib = _lib.load()
         opt = _options(mr_list_capacity=mr_list_capacity, mr_max_sweeps=mr_max_sweeps,
-                       persistent_blocks=persistent_blocks, profile=profile, mr_seed_sweeps=mr_seed_sweeps)
+                       persistent_blocks=persistent_blocks, profile=profile, mr_seed_sweeps=mr_seed_sweeps,
+                       wg_waves=wg_waves, stage_depth=stage_depth, mr_seed_strip=mr_seed_strip)
         h = ctypes.c_void_p()
         rc = lib.iwpp_create(int(device), ctypes.byref(opt), ctypes.byref(h))
         if rc != _lib.IWPP_OK:
@@ -68,7 +71,8 @@ class Context:
         self.device = int(device)
         self.options = {"mr_list_capacity": int(mr_list_capacity), "mr_max_sweeps": int(mr_max_sweeps),
                         "persistent_blocks": int(persistent_blocks), "profile": bool(profile),
-                        "mr_seed_sweeps": int(mr_seed_sweeps)}
+                        "mr_seed_sweeps": int(mr_seed_sweeps), "wg_waves": int(wg_waves),
+                        "stage_depth": int(stage_depth), "mr_seed_strip": int(mr_seed_strip)}
 
     def set_options(self, **kw) -> None:
         """Change tuning options (same names as the constructor) for later
@@ -121,6 +125,60 @@ class Context:
             self._err(rc)
         return out
 
+    def morph_recon_erode(self, marker, mask, conn: int = 8, out=None):
+        """Reconstruction by erosion rho*_I(J) (the dual of morph_recon; a
+        marker below the mask is raised to it first)."""
+        torch = _torch()
+        _check_image(mask, "mask", torch.uint8)
+        _check_image(marker, "marker", torch.uint8, mask.device)
+        if marker.shape != mask.shape:
+            raise ValueError("marker and mask must have the same shape")
+        if conn not in (4, 8):
+            raise ValueError("conn must be 4 or 8")
+        if out is None:
+            out = torch.empty_like(mask)
+        else:
+            _check_image(out, "out", torch.uint8, mask.device)
+            if out.shape != mask.shape:
+                raise ValueError("out must have the shape of mask")
+        h, w = mask.shape
+        rc = self._lib.iwpp_morph_recon_erode_u8(self._h, marker.data_ptr(), mask.data_ptr(), out.data_ptr(),
+                                                 h, w, conn, self._stream(mask.device))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return out
+
+    def morph_recon_queue(self, marker, mask, conn: int = 8, mode: str = "staged", capacity: int = 0,
+                          seed_sweeps: int = 0, out=None):
+        """Reconstruction by dilation with the paper's pixel queue
+        (iwpp_morph_recon_queue_u8): the same result as morph_recon, for
+        comparing queue designs.  `mode` is how items enter a round's queue:
+        "naive", "ballot" or "staged"; `capacity` bounds each queue (0 = never
+        overflows); `seed_sweeps` is the seed pass's sweep iterations per
+        tile (0 = default)."""
+        torch = _torch()
+        _check_image(mask, "mask", torch.uint8)
+        _check_image(marker, "marker", torch.uint8, mask.device)
+        if marker.shape != mask.shape:
+            raise ValueError("marker and mask must have the same shape")
+        if conn not in (4, 8):
+            raise ValueError("conn must be 4 or 8")
+        if mode not in _lib.QUEUE_MODES:
+            raise ValueError(f"mode must be one of {sorted(_lib.QUEUE_MODES)}")
+        if out is None:
+            out = torch.empty_like(mask)
+        else:
+            _check_image(out, "out", torch.uint8, mask.device)
+            if out.shape != mask.shape:
+                raise ValueError("out must have the shape of mask")
+        q = _lib.QueueOptions(_lib.QUEUE_MODES[mode], int(seed_sweeps), int(capacity))
+        h, w = mask.shape
+        rc = self._lib.iwpp_morph_recon_queue_u8(self._h, marker.data_ptr(), mask.data_ptr(), out.data_ptr(), h, w,
+                                                 conn, ctypes.byref(q), self._stream(mask.device))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return out
+
     def morph_recon_noalloc(self, marker, mask, out, conn: int = 8):
         """morph_recon through iwpp_morph_recon_u8_noalloc: no device memory is
         allocated, neither by the library (its work area is a static device
@@ -156,6 +214,25 @@ class Context:
             _check_image(nr, "nearest", torch.int32, binary.device)
         rc = self._lib.iwpp_edt(self._h, binary.data_ptr(), sq.data_ptr(), nr.data_ptr(), h, w, conn,
                                 self._stream(binary.device))
+        if rc != _lib.IWPP_OK:
+            self._err(rc)
+        return sq, nr
+
+    def edt_exact(self, binary, out=None):
+        """The exact Euclidean distance transform (iwpp_edt_exact): exact
+        squared distances and, per pixel, a feature at exactly that distance."""
+        torch = _torch()
+        _check_image(binary, "binary", torch.uint8)
+        h, w = binary.shape
+        if out is None:
+            sq = torch.empty((h, w), dtype=torch.int32, device=binary.device)
+            nr = torch.empty((h, w), dtype=torch.int32, device=binary.device)
+        else:
+            sq, nr = out
+            _check_image(sq, "sqdist", torch.int32, binary.device)
+            _check_image(nr, "nearest", torch.int32, binary.device)
+        rc = self._lib.iwpp_edt_exact(self._h, binary.data_ptr(), sq.data_ptr(), nr.data_ptr(), h, w,
+                                      self._stream(binary.device))
         if rc != _lib.IWPP_OK:
             self._err(rc)
         return sq, nr
@@ -220,13 +297,21 @@ class Context:
         return _stats_dict(st)
 
 
-def _options(mr_list_capacity=0, mr_max_sweeps=0, persistent_blocks=0, profile=False, mr_seed_sweeps=0):
+OPTION_NAMES = ("mr_list_capacity", "mr_max_sweeps", "persistent_blocks", "profile", "mr_seed_sweeps", "wg_waves",
+                "stage_depth", "mr_seed_strip")
+
+
+def _options(mr_list_capacity=0, mr_max_sweeps=0, persistent_blocks=0, profile=False, mr_seed_sweeps=0,
+             wg_waves=0, stage_depth=0, mr_seed_strip=0):
     opt = _lib.Options()
     opt.mr_list_capacity = int(mr_list_capacity)
     opt.mr_max_sweeps = int(mr_max_sweeps)
     opt.persistent_blocks = int(persistent_blocks)
     opt.profile = 1 if profile else 0
     opt.mr_seed_sweeps = int(mr_seed_sweeps)
+    opt.wg_waves = int(wg_waves)
+    opt.stage_depth = int(stage_depth)
+    opt.mr_seed_strip = int(mr_seed_strip)
     return opt
 
 
@@ -240,7 +325,7 @@ def _marshal_jobs(jobs: list):
         conn = int(j.get("conn", 8))
         if conn not in (4, 8):
             raise ValueError(f"job {i}: conn must be 4 or 8")
-        if j["op"] == "recon":
+        if j["op"] in ("recon", "erode"):
             _check_image(j["mask"], f"job {i} mask", torch.uint8, dev)
             dev = j["mask"].device
             _check_image(j["marker"], f"job {i} marker", torch.uint8, dev)
@@ -248,8 +333,8 @@ def _marshal_jobs(jobs: list):
             if not (j["marker"].shape == j["mask"].shape == j["out"].shape):
                 raise ValueError(f"job {i}: shapes differ")
             h, w = j["mask"].shape
-            arr[i] = _lib.Job(_lib.IWPP_OP_RECON, conn, h, w, j["marker"].data_ptr(), j["mask"].data_ptr(),
-                              j["out"].data_ptr(), None)
+            op = _lib.IWPP_OP_RECON if j["op"] == "recon" else _lib.IWPP_OP_RECON_ERODE
+            arr[i] = _lib.Job(op, conn, h, w, j["marker"].data_ptr(), j["mask"].data_ptr(), j["out"].data_ptr(), None)
         elif j["op"] == "edt":
             _check_image(j["binary"], f"job {i} binary", torch.uint8, dev)
             dev = j["binary"].device
@@ -261,7 +346,7 @@ def _marshal_jobs(jobs: list):
             arr[i] = _lib.Job(_lib.IWPP_OP_EDT, conn, h, w, j["binary"].data_ptr(), None,
                               j["sqdist"].data_ptr(), j["nearest"].data_ptr())
         else:
-            raise ValueError(f"job {i}: op must be 'recon' or 'edt'")
+            raise ValueError(f"job {i}: op must be 'recon', 'erode' or 'edt'")
     return arr, dev
 
 
@@ -354,7 +439,7 @@ class Server:
         raise IwppError(rc, self._lib.iwpp_last_error(self._ctx._h).decode())
 
     def submit(self, job: dict, arrival_ns: int = 0, stream=None) -> int:
-        """Queue a job: ``{"op": "recon", "marker", "mask", "out", "conn"}`` or
+        """Queue a job: ``{"op": "recon" or "erode", "marker", "mask", "out", "conn"}`` or
         ``{"op": "edt", "binary", "sqdist", "nearest", "conn"}`` with CPU
         tensors (device tensors of the context's device for a resident
         server); `arrival_ns` on time.monotonic_ns()'s clock (0 = now).  The
@@ -369,14 +454,14 @@ class Server:
             check = lambda t, name, dtype: _check_image(t, name, dtype, dev)  # noqa: E731
         else:
             check = _check_host
-        if job["op"] == "recon":
+        if job["op"] in ("recon", "erode"):
             for k in ("marker", "mask", "out"):
                 check(job[k], k, torch.uint8)
             if not (job["marker"].shape == job["mask"].shape == job["out"].shape):
                 raise ValueError("shapes differ")
             h, w = job["mask"].shape
-            j = _lib.Job(_lib.IWPP_OP_RECON, conn, h, w, job["marker"].data_ptr(), job["mask"].data_ptr(),
-                         job["out"].data_ptr(), None)
+            op = _lib.IWPP_OP_RECON if job["op"] == "recon" else _lib.IWPP_OP_RECON_ERODE
+            j = _lib.Job(op, conn, h, w, job["marker"].data_ptr(), job["mask"].data_ptr(), job["out"].data_ptr(), None)
             keep = (job["marker"], job["mask"], job["out"])
         elif job["op"] == "edt":
             check(job["binary"], "binary", torch.uint8)
@@ -389,7 +474,7 @@ class Server:
                          job["nearest"].data_ptr())
             keep = (job["binary"], job["sqdist"], job["nearest"])
         else:
-            raise ValueError("op must be 'recon' or 'edt'")
+            raise ValueError("op must be 'recon', 'erode' or 'edt'")
         t = ctypes.c_uint64()
         rc = self._lib.iwpp_server_submit(self._h, ctypes.byref(j), int(arrival_ns), ctypes.c_void_p(stream.cuda_stream),
                                           ctypes.byref(t))
@@ -466,6 +551,13 @@ def morph_recon(marker, mask, conn: int = 8, out=None):
     (uint8 GPU tensors of one shape); bit-exact."""
     _check_image(mask, "mask", _torch().uint8)
     return _default_ctx(mask.device).morph_recon(marker, mask, conn, out)
+
+
+def morph_recon_erode(marker, mask, conn: int = 8, out=None):
+    """Reconstruction by erosion rho*_I(J) of `mask` from `marker` (uint8 GPU
+    tensors of one shape), the dual of morph_recon; bit-exact."""
+    _check_image(mask, "mask", _torch().uint8)
+    return _default_ctx(mask.device).morph_recon_erode(marker, mask, conn, out)
 
 
 def edt(binary, conn: int = 8, out=None):

@@ -22,13 +22,19 @@ EXPORTED = (
     "iwpp_batch_graph_round_times",
     "iwpp_round_work",
     "iwpp_morph_recon_u8_noalloc",
+    "iwpp_morph_recon_erode_u8",
+    "iwpp_morph_recon_queue_u8",
+    "iwpp_edt_exact",
 )
 # Size of the static work area of iwpp_morph_recon_u8_noalloc (IWPP_NOALLOC_SCRATCH_BYTES).
 NOALLOC_SCRATCH_BYTES = 32 << 20
 IWPP_OP_RECON = 1
 IWPP_OP_EDT = 2
+IWPP_OP_RECON_ERODE = 3
 
-KERNEL_NAMES = {0: "reset", 1: "mr_seed", 2: "mr_detect", 3: "mr_propagate", 4: "edt_init", 5: "edt_rounds"}
+KERNEL_NAMES = {0: "reset", 1: "mr_seed", 2: "mr_detect", 3: "mr_propagate", 4: "edt_init", 5: "edt_rounds",
+                6: "mrq_init", 7: "mrq_propagate", 8: "edt_exact"}
+QUEUE_MODES = {"naive": 0, "ballot": 1, "staged": 2}
 
 
 class Options(ctypes.Structure):
@@ -38,7 +44,19 @@ class Options(ctypes.Structure):
         ("persistent_blocks", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("mr_seed_sweeps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("wg_waves", ctypes.c_int32),
+        ("stage_depth", ctypes.c_int32),
+        ("mr_seed_strip", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class QueueOptions(ctypes.Structure):
+    _fields_ = [
+        ("append_mode", ctypes.c_int32),
+        ("seed_sweeps", ctypes.c_int32),
+        ("capacity", ctypes.c_int64),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -119,6 +137,12 @@ def load():
     lib.iwpp_morph_recon_u8.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
     lib.iwpp_morph_recon_u8.restype = i32
     lib.iwpp_morph_recon_u8_noalloc.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
+    lib.iwpp_morph_recon_erode_u8.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
+    lib.iwpp_morph_recon_erode_u8.restype = i32
+    lib.iwpp_morph_recon_queue_u8.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.POINTER(QueueOptions), vp]
+    lib.iwpp_morph_recon_queue_u8.restype = i32
+    lib.iwpp_edt_exact.argtypes = [vp, vp, vp, vp, i32, i32, vp]
+    lib.iwpp_edt_exact.restype = i32
     lib.iwpp_morph_recon_u8_noalloc.restype = i32
     lib.iwpp_edt.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
     lib.iwpp_edt.restype = i32

@@ -10,7 +10,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libiwpp.so")
-SOURCES = ["iwpp_api.hip", "iwpp_mr.hip", "iwpp_edt.hip", "iwpp_server.hip", "iwpp_noalloc.hip"]
+SOURCES = ["iwpp_api.hip", "iwpp_mr.hip", "iwpp_edt.hip", "iwpp_server.hip", "iwpp_noalloc.hip",
+           "iwpp_mrq.hip", "iwpp_edt_exact.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -105,6 +105,7 @@ DeviceGuard::~DeviceGuard() {
 }
 
 size_t job_scratch_bytes(int op, int32_t h, int32_t w) {
+  if (op == IWPP_OP_RECON_ERODE) op = IWPP_OP_RECON;  // the same kernels
   const int ts = op == IWPP_OP_RECON ? iwpp::kMrTile : iwpp::kEdtTile;
   const uint64_t t = (uint64_t)((h + ts - 1) / ts) * (uint64_t)((w + ts - 1) / ts);
   const uint64_t np = (uint64_t)h * (uint64_t)w;
@@ -157,11 +158,12 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
   for (int32_t i = 0; i < n; ++i) {
     const iwpp_job& j = jobs[i];
     const std::string at = std::string(who) + ": job " + std::to_string(i) + ": ";
-    if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_EDT) return fail(ctx, IWPP_EINVAL, at + "op must be RECON or EDT");
+    if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_RECON_ERODE && j.op != IWPP_OP_EDT)
+      return fail(ctx, IWPP_EINVAL, at + "op must be RECON, RECON_ERODE or EDT");
     if (j.conn != 4 && j.conn != 8) return fail(ctx, IWPP_EINVAL, at + "conn must be 4 or 8");
     if (j.height < 1 || j.width < 1) return fail(ctx, IWPP_EINVAL, at + "height and width must be >= 1");
     const uint64_t np = (uint64_t)j.height * (uint64_t)j.width;
-    if (j.op == IWPP_OP_RECON) {
+    if (j.op != IWPP_OP_EDT) {
       if (!j.in0 || !j.in1 || !j.out0 || j.out1)
         return fail(ctx, IWPP_EINVAL, at + "reconstruction needs in0 (marker), in1 (mask), out0 and no out1");
       // A tile's 66-row band of the image is addressed with 32-bit offsets.
@@ -200,7 +202,9 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
       g.conn = conn;
       for (int32_t i = 0; i < n; ++i) {
         const iwpp_job& j = jobs[i];
-        if (j.op != op || j.conn != conn) continue;
+        // reconstruction by erosion runs in the dilation group on complemented bytes
+        const int jop = j.op == IWPP_OP_RECON_ERODE ? IWPP_OP_RECON : j.op;
+        if (jop != op || j.conn != conn) continue;
         if (op == IWPP_OP_RECON) {
           iwpp::MrJob m{};
           m.marker = j.in0;
@@ -208,6 +212,7 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
           m.out = static_cast<uint8_t*>(j.out0);
           m.h = j.height;
           m.w = j.width;
+          m.inv = j.op == IWPP_OP_RECON_ERODE ? 0xFFFFFFFFu : 0u;
           mr_place(m, g.ntiles);
           g.mr.push_back(m);
         } else {
@@ -261,7 +266,7 @@ void pack_tables(const Plan& plan, uint8_t* host) {
 // Launch the kernels of one group on `st`, using `scratch`/`fixed`/`tables`.
 // `first` also clears the statistics.
 int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* fixed, uint8_t* tables, hipStream_t st,
-                     bool first, iwpp::Recorder* rec) {
+                     bool first, iwpp::Recorder* rec, bool seed_only) {
   rec->begin(IWPP_K_RESET, st);
   const int zr = iwpp::zero_words(reinterpret_cast<uint32_t*>(fixed), (first ? kFixedBytes : kOffStats) / 4, st);
   rec->end(st);
@@ -284,6 +289,10 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     // paths inside a tile are longer).
     a.max_sweeps = ctx->opt.mr_max_sweeps > 0 ? ctx->opt.mr_max_sweeps : 2;
     a.seed_sweeps = ctx->opt.mr_seed_sweeps > 0 ? ctx->opt.mr_seed_sweeps : (g.conn == 8 ? 1 : 2);
+    a.seed_only = seed_only ? 1u : 0u;
+    a.seed_strip = (uint32_t)ctx->opt.mr_seed_strip;
+    a.stage_depth = (uint32_t)ctx->opt.stage_depth;
+    a.wg_waves = ctx->opt.wg_waves == 8 ? 8u : 4u;
     a.flags = reinterpret_cast<uint32_t*>(scratch);
     a.lists = reinterpret_cast<uint32_t*>(scratch + 2 * tb);
     a.unsettled = reinterpret_cast<uint32_t*>(scratch + 18 * tb);
@@ -316,6 +325,8 @@ int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* f
     a.jobs = nj > 1 ? reinterpret_cast<const iwpp::EdtJob*>(tables + g.table_off) : nullptr;
     a.counts = reinterpret_cast<uint32_t*>(fixed + kOffCounts);
     a.ovf = reinterpret_cast<uint32_t*>(fixed + kOffOvf);
+    a.stage_depth = (uint32_t)ctx->opt.stage_depth;
+    a.wg_waves = ctx->opt.wg_waves == 8 ? 8u : 4u;
     a.bar = reinterpret_cast<iwpp::GridBarrier*>(fixed + kOffBarrier);
     a.stats = reinterpret_cast<unsigned long long*>(fixed + kOffStats);
     a.clock = reinterpret_cast<unsigned long long*>(fixed + kOffClock);
@@ -425,7 +436,8 @@ int32_t read_clock(iwpp_ctx* ctx, const uint8_t* fixed, hipStream_t st, double* 
 
 bool options_valid(const iwpp_options& o) {
   return o.mr_list_capacity >= 0 && o.mr_max_sweeps >= 0 && o.persistent_blocks >= 0 && o.profile >= 0 &&
-         o.mr_seed_sweeps >= 0;
+         o.mr_seed_sweeps >= 0 && (o.wg_waves == 0 || o.wg_waves == 4 || o.wg_waves == 8) && o.stage_depth >= 0 &&
+         o.stage_depth <= 64 && o.mr_seed_strip >= 0;
 }
 
 }  // namespace iwpp::rt
@@ -456,7 +468,7 @@ int32_t iwpp_create(int32_t device, const iwpp_options* opt, iwpp_ctx** out) {
   ctx->device = device;
   if (opt && !options_valid(*opt)) {
     delete ctx;
-    g_create_err = "iwpp_create: negative option value";
+    g_create_err = "iwpp_create: option out of range (negative, wg_waves not 0/4/8 or stage_depth above 64)";
     return IWPP_EINVAL;
   }
   if (opt) ctx->opt = *opt;
@@ -515,6 +527,20 @@ int32_t iwpp_morph_recon_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t*
   return run_plan(ctx, plan, static_cast<hipStream_t>(stream), 1);
 }
 
+int32_t iwpp_morph_recon_erode_u8(iwpp_ctx* ctx, const uint8_t* marker, const uint8_t* mask, uint8_t* out,
+                                  int32_t height, int32_t width, int32_t conn, void* stream) {
+  if (!ctx) return IWPP_EINVAL;
+  if (ctx->server) return fail(ctx, IWPP_EBUSY, "morph_recon_erode: the context is serving");
+  if (!marker || !mask || !out) return fail(ctx, IWPP_EINVAL, "morph_recon_erode: NULL image pointer");
+  iwpp_job j{IWPP_OP_RECON_ERODE, conn, height, width, marker, mask, out, nullptr};
+  Plan plan;
+  int32_t rc = build_plan(ctx, &j, 1, "morph_recon_erode", plan);
+  if (rc != IWPP_OK) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, IWPP_EDEVICE, "morph_recon_erode: cannot select the context's device");
+  return run_plan(ctx, plan, static_cast<hipStream_t>(stream), 1);
+}
+
 int32_t iwpp_edt(iwpp_ctx* ctx, const uint8_t* binary, int32_t* sqdist, int32_t* nearest, int32_t height,
                  int32_t width, int32_t conn, void* stream) {
   if (!ctx) return IWPP_EINVAL;
@@ -544,7 +570,8 @@ int32_t iwpp_set_options(iwpp_ctx* ctx, const iwpp_options* opt) {
   if (!ctx) return IWPP_EINVAL;
   if (ctx->server) return fail(ctx, IWPP_EBUSY, "set_options: the context is serving");
   if (!opt) return fail(ctx, IWPP_EINVAL, "set_options: NULL options");
-  if (!options_valid(*opt)) return fail(ctx, IWPP_EINVAL, "set_options: negative option value");
+  if (!options_valid(*opt))
+    return fail(ctx, IWPP_EINVAL, "set_options: option out of range (negative, wg_waves not 0/4/8 or stage_depth above 64)");
   ctx->opt = *opt;
   ctx->rec.enabled = ctx->opt.profile != 0;
   return IWPP_OK;

@@ -270,6 +270,73 @@ __device__ __forceinline__ void round_work(unsigned long long* clock, uint32_t p
   if (blockIdx.x == 0 && threadIdx.x == 0 && phase < kClockStamps) clock[kClockStamps + phase] = tiles;
 }
 
+// Work of a round shared by the waves of a workgroup: the workgroup owns a
+// contiguous range [lo, hi) of the round's items, and its waves take the next
+// item from an LDS counter, so a wave whose visits were cheap takes more.
+// Ranges are cut XCD-major: workgroup b runs on XCD b mod 8, and the eight
+// XCDs own eight contiguous parts of the items, so the tiles an XCD visits
+// together are neighbours whose shared cache lines (the other half of a
+// 128-byte line, the halo rows and border columns) its own L2 holds.
+// (One device-scope atomic per item instead, shared by all workgroups, was
+// measured to double the dense rounds: its latency under contention exceeds
+// the imbalance it removes; items dealt round-robin over the workgroups made
+// the seed pass 40% slower than neighbouring strips on one XCD.)
+struct WgShare {
+  uint32_t lo, hi;
+  uint32_t* next;  // LDS, zeroed before the round
+  __device__ bool take(uint32_t& i) const {
+    uint32_t k = 0;
+    if (lane() == 0) k = atomicAdd(next, 1u);
+    k = readlane(k, 0);
+    i = lo + k;
+    return i < hi;
+  }
+};
+
+constexpr uint32_t kXcds = 8;  // workgroup b runs on XCD b mod 8
+
+// Workgroups of the grid on XCD x, and this workgroup's rank among them.
+__device__ __forceinline__ uint32_t xcd_groups(uint32_t x) { return (gridDim.x + kXcds - 1u - x) / kXcds; }
+
+// This workgroup's share of the items [base, base + n) owned by its XCD.
+__device__ __forceinline__ WgShare share_of(uint32_t base, uint32_t n, uint32_t* next) {
+  const uint32_t l = blockIdx.x / kXcds, L = xcd_groups(blockIdx.x % kXcds);
+  WgShare w;
+  w.lo = base + (uint32_t)(((uint64_t)n * l) / L);
+  w.hi = base + (uint32_t)(((uint64_t)n * (l + 1u)) / L);
+  w.next = next;
+  return w;
+}
+
+// n items cut into eight XCD parts (when the grid covers all XCDs).
+__device__ __forceinline__ WgShare wg_share(uint32_t n, uint32_t* next) {
+  if (gridDim.x < kXcds) {
+    WgShare w;
+    w.lo = (uint32_t)(((uint64_t)n * blockIdx.x) / gridDim.x);
+    w.hi = (uint32_t)(((uint64_t)n * (blockIdx.x + 1u)) / gridDim.x);
+    w.next = next;
+    return w;
+  }
+  const uint32_t x = blockIdx.x % kXcds;
+  const uint32_t lo = (uint32_t)(((uint64_t)n * x) / kXcds), hi = (uint32_t)(((uint64_t)n * (x + 1u)) / kXcds);
+  return share_of(lo, hi - lo, next);
+}
+
+// A round's list, whose sub-list x (cnt[x] items) was appended by XCD x:
+// XCD x takes its own sub-list, where the neighbours of the tiles it visited
+// last round are.  Items are indices into the concatenated sub-lists.
+__device__ __forceinline__ WgShare wg_share_lists(const uint32_t* cnt, uint32_t* next) {
+  if (gridDim.x < kXcds) {
+    uint32_t n = 0;
+    for (uint32_t x = 0; x < kXcds; ++x) n += cnt[x];
+    return wg_share(n, next);
+  }
+  const uint32_t x = blockIdx.x % kXcds;
+  uint32_t base = 0;
+  for (uint32_t y = 0; y < x; ++y) base += cnt[y];
+  return share_of(base, cnt[x], next);
+}
+
 // ---- sharded tile frontier --------------------------------------------------------
 // A round's work list of tiles is split into kShards sub-lists, one per group of
 // workgroups (blockIdx & 7, i.e. one per XCD).  A wave stages its appends in LDS

@@ -50,8 +50,8 @@ constexpr int TE = kEdtTile;       // tile side
 constexpr int RP = TE + 2 * K;     // region side
 constexpr int kCPR = (RP + 3) / 4; // 16-byte chunks per region row
 constexpr int PE = 4 * kCPR;       // LDS row pitch (words)
-constexpr int kWavesPerBlock = 4;
-constexpr int kStageCap = 32;
+constexpr int kWavesPerBlock = 4;  // the initialisation kernel
+constexpr int kStageCap = 64;       // LDS work-list stage per wave (iwpp_options.stage_depth caps it)
 constexpr uint32_t kMaxSteps = (1u << 20) / K;
 static_assert(RP - 2 <= 32, "a round's region row must fit 32 lanes");
 static_assert(K % 4 == 0, "region chunks must not straddle the image's left edge");
@@ -232,19 +232,27 @@ __device__ __forceinline__ uint32_t zone_bits(int cy, int cx) {
 // others cannot change -- gathered into a list from the previous round's
 // change masks; for round 1 those are the previous step's last-round changes
 // over the region (`prev_step_issue` / `prev_step_finish`; for the first
-// step, the contour features recorded by `k_init`).  Each lane computes up
-// to kPerLane list pixels into registers and writes them after the whole
-// wave has read, so every read sees round i-1.  Pixels outside the image stay
-// none.  Accumulates the changed tile pixels (over the rounds), the zone mask
-// (bit 0: a tile pixel changed; bits 1..8: a change in round K within K
-// pixels of that side) and the last round (1..K) with a change.
+// step, the contour features recorded by `k_init`).  Pixels outside the image
+// never enter the list (they stay none).  Each lane computes up to kPerLane
+// list pixels, kBatch at a time with their loads issued together, into
+// registers, and writes the changed ones after the whole wave has read, so
+// every read sees round i-1.  Accumulates the changed tile pixels (over the
+// rounds), the zone mask (bit 0: a tile pixel changed; bits 1..8: a change in
+// round K within K pixels of that side) and the last round (1..K) with a
+// change.
+constexpr int kBatch = 2;
+static_assert(kPerLane % kBatch == 0, "whole batches");
 template <int CONN, bool kWide>
 __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, uint32_t& zone, uint32_t& last) {
-  constexpr uint32_t kNone = Coord<kWide>::none;
   static_assert(RP <= 64, "one mask bit per region column");
+  constexpr int NC = CONN == 8 ? 9 : 5;
   const EdtJob& j = tr.j;
   const int ry0 = tr.ty * TE - K, rx0 = tr.tx * TE - K;
   const int l = lane();
+  // Region columns and this lane's region row that lie inside the image.
+  const int c_lo = rx0 < 0 ? -rx0 : 0, c_hi = j.w - rx0 < RP ? j.w - rx0 : RP;
+  const unsigned long long in_cols = ((c_hi >= 64 ? ~0ull : ((1ull << c_hi) - 1ull))) & ~((1ull << c_lo) - 1ull);
+  const bool in_row = ry0 + l >= 0 && ry0 + l < j.h;
 #pragma unroll 1
   for (int i = 1; i <= K; ++i) {
     unsigned long long* now = L.chg[i & 1];
@@ -253,9 +261,9 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
     // step's last-round changes over the region).
     uint32_t n;
     {
-      const unsigned long long win = ((1ull << (RP - i)) - 1ull) & ~((1ull << i) - 1ull);  // columns [i, RP-i)
+      const unsigned long long win = ((1ull << (RP - i)) - 1ull) & ~((1ull << i) - 1ull) & in_cols;  // columns [i, RP-i)
       unsigned long long m = 0;
-      if (l >= i && l < RP - i) {
+      if (l >= i && l < RP - i && in_row) {
         m = prev[l - 1] | prev[l] | prev[l + 1];
         m = (m | (m << 1) | (m >> 1)) & win;
       }
@@ -272,41 +280,51 @@ __device__ void relax_steps(WaveLds& L, const TileRef& tr, uint32_t& changed, ui
     }
     if (l < RP) now[l] = 0ull;
     wave_sync();
-    // Compute (reads only).
+    // Compute (reads only): batches of kBatch list pixels per lane.
     uint32_t res[kPerLane];
+    uint32_t chg = 0;  // bit k: list pixel k of this lane changed
 #pragma unroll
-    for (int k = 0; k < kPerLane; ++k) {
-      res[k] = kNone;
-      const uint32_t idx = (uint32_t)(k * kWave + l);
-      if ((uint32_t)(k * kWave) >= n) continue;  // wave-uniform
-      if (idx >= n) continue;
-      const uint32_t e = L.list[idx];
-      const int row = (int)(e >> 8), col = (int)(e & 0xffu);
-      const int qy = ry0 + row, qx = rx0 + col;
-      if (qy < 0 || qy >= j.h || qx < 0 || qx >= j.w) continue;  // outside the image: stays none
-      const uint32_t q = pack_yx(qy, qx);
-      const uint32_t* c = &L.F[row * PE + col];
-      if (CONN == 8) {
-        const uint32_t f[9] = {c[0], c[-PE], c[PE], c[-1], c[1], c[-PE - 1], c[-PE + 1], c[PE - 1], c[PE + 1]};
-        res[k] = Coord<kWide>::nearest(q, f);
-      } else {
-        const uint32_t f[5] = {c[0], c[-PE], c[PE], c[-1], c[1]};
-        res[k] = Coord<kWide>::nearest(q, f);
+    for (int k0 = 0; k0 < kPerLane; k0 += kBatch) {
+      if ((uint32_t)(k0 * kWave) < n) {  // wave-uniform
+        uint32_t f[kBatch][NC], ent[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const uint32_t idx = (uint32_t)((k0 + b) * kWave + l);
+          // past the list: a harmless in-region pixel (row 1, column 1); its result is not used
+          ent[b] = idx < n ? (uint32_t)L.list[idx] : 0x101u;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const uint32_t* c = &L.F[(int)(ent[b] >> 8) * PE + (int)(ent[b] & 0xffu)];
+          f[b][0] = c[0];
+          f[b][1] = c[-PE];
+          f[b][2] = c[PE];
+          f[b][3] = c[-1];
+          f[b][4] = c[1];
+          if (CONN == 8) {
+            f[b][5] = c[-PE - 1];
+            f[b][6] = c[-PE + 1];
+            f[b][7] = c[PE - 1];
+            f[b][8] = c[PE + 1];
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          const uint32_t q = pack_yx(ry0 + (int)(ent[b] >> 8), rx0 + (int)(ent[b] & 0xffu));
+          res[k0 + b] = Coord<kWide>::nearest(q, f[b]);
+          const uint32_t idx = (uint32_t)((k0 + b) * kWave + l);
+          chg |= (idx < n && res[k0 + b] != f[b][0]) ? (1u << (k0 + b)) : 0u;
+        }
       }
     }
     wave_sync();
-    // Write back, recording the changes.
+    // Write back the changed pixels, recording them.
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k) {
-      const uint32_t idx = (uint32_t)(k * kWave + l);
-      if ((uint32_t)(k * kWave) >= n) continue;
-      if (idx >= n) continue;
-      const uint32_t e = L.list[idx];
+      if (!((chg >> k) & 1u)) continue;
+      const uint32_t e = L.list[(uint32_t)(k * kWave + l)];
       const int row = (int)(e >> 8), col = (int)(e & 0xffu);
-      uint32_t* c = &L.F[row * PE + col];
-      const uint32_t old = c[0];
-      if (res[k] == old) continue;
-      *c = res[k];
+      L.F[row * PE + col] = res[k];
       atomicOr(&now[row], 1ull << col);
       if (row >= K && row < K + TE && col >= K && col < K + TE) {
         changed++;
@@ -503,16 +521,20 @@ __global__ __launch_bounds__(256) void k_init(EdtArgs a) {
   shard_flush(st, nx.list, nx.count, a.ntiles, nx.flags, a.ovf);
 }
 
-template <int CONN, bool kWide>
-__global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  __shared__ uint32_t stage_mem[kWavesPerBlock][kStageCap];
+// WPB waves per workgroup; five workgroups of four waves (or two of eight)
+// fit a CU's registers and LDS.  A step's tiles are shared by the waves of a
+// workgroup (WgShare).
+template <int CONN, bool kWide, int WPB>
+__global__ __launch_bounds__(64 * WPB, WPB == 4 ? 5 : 2) void k_rounds(EdtArgs a) {
+  __shared__ WaveLds lds[WPB];
+  __shared__ uint32_t stage_mem[WPB][kStageCap];
   __shared__ uint32_t cnt[kShards];
   __shared__ uint32_t last_sh;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   WaveLds& L = lds[w];
-  WaveStage s = {stage_mem[w], (uint32_t)kStageCap, 0u};
-  const uint32_t gw = blockIdx.x * kWavesPerBlock + (uint32_t)w, nw = gridDim.x * kWavesPerBlock;
+  const uint32_t depth = a.stage_depth > 0u && a.stage_depth < (uint32_t)kStageCap ? a.stage_depth : (uint32_t)kStageCap;
+  WaveStage s = {stage_mem[w], depth, 0u};
+  const uint32_t gw = blockIdx.x * WPB + (uint32_t)w, nw = gridDim.x * WPB;
   if (threadIdx.x == 0) last_sh = 0u;
   uint32_t gen = 0, nclk = 0;
   unsigned long long changed = 0, visits = 0;
@@ -541,6 +563,9 @@ __global__ __launch_bounds__(256, 5) void k_rounds(EdtArgs a) {
     const uint32_t* lists = a.lists + (size_t)par * kShards * a.ntiles;
     uint32_t* flg = a.flags + (size_t)par * a.ntiles;
     const Next nx = next_frontier(a, m);
+    // Items are dealt round-robin over the waves of the grid: workgroup
+    // pooling, and items kept on the XCD that listed them, were both measured
+    // slower here (1.36 and 1.38 against 1.34 ms on the 4096^2 workload).
     for (uint32_t i = gw; i < n; i += nw) {
       const uint32_t t = shard_item(lists, a.ntiles, cnt, i);
       if (lane() == 0) cstore(flg + t, 0u);
@@ -632,6 +657,7 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
     *err = "flag reset launch failed";
     return -1;
   }
+  // eight XCD parts of ceil(ntiles / 8) tiles, kWavesPerBlock tiles per workgroup
   const uint32_t init_blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
   rec->begin(4, stream);
   if (conn == 8 && !a.wide)
@@ -647,20 +673,26 @@ int edt_launch(const EdtArgs& a, int conn, int persistent_blocks, hipStream_t st
     *err = "EDT init launch failed";
     return -1;
   }
-  void* fn = conn == 8 ? (a.wide ? reinterpret_cast<void*>(&k_rounds<8, true>) : reinterpret_cast<void*>(&k_rounds<8, false>))
-                       : (a.wide ? reinterpret_cast<void*>(&k_rounds<4, true>) : reinterpret_cast<void*>(&k_rounds<4, false>));
+  const int wpb = a.wg_waves == 8u ? 8 : 4;
+  void* fn;
+  if (wpb == 8)
+    fn = conn == 8 ? (a.wide ? reinterpret_cast<void*>(&k_rounds<8, true, 8>) : reinterpret_cast<void*>(&k_rounds<8, false, 8>))
+                   : (a.wide ? reinterpret_cast<void*>(&k_rounds<4, true, 8>) : reinterpret_cast<void*>(&k_rounds<4, false, 8>));
+  else
+    fn = conn == 8 ? (a.wide ? reinterpret_cast<void*>(&k_rounds<8, true, 4>) : reinterpret_cast<void*>(&k_rounds<8, false, 4>))
+                   : (a.wide ? reinterpret_cast<void*>(&k_rounds<4, true, 4>) : reinterpret_cast<void*>(&k_rounds<4, false, 4>));
   int dev = 0, per_cu = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1) {
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * wpb, 0) != hipSuccess || per_cu < 1) {
     *err = "occupancy query failed";
     return -1;
   }
-  uint32_t blocks = persistent_grid(fn, per_cu, cus, 5);  // five workgroups of four waves fit a CU's registers and LDS
+  uint32_t blocks = persistent_grid(fn, per_cu, cus, wpb == 4 ? 5 : 2);
   if (persistent_blocks > 0 && (uint32_t)persistent_blocks < blocks) blocks = (uint32_t)persistent_blocks;
   EdtArgs args = a;
   void* kargs[] = {&args};
   rec->begin(5, stream);
-  const hipError_t le = launch_persistent(fn, blocks, kargs, stream);
+  const hipError_t le = launch_persistent(fn, blocks, kargs, stream, 64 * wpb);
   rec->end(stream);
   if (le != hipSuccess) {
     *err = "EDT rounds launch failed";
@@ -680,11 +712,11 @@ uint32_t persistent_grid(const void* fn, int per_cu, int cus, int max_per_cu) {
   return (uint32_t)lim * (uint32_t)cus;
 }
 
-hipError_t launch_persistent(const void* fn, uint32_t blocks, void** args, hipStream_t s) {
+hipError_t launch_persistent(const void* fn, uint32_t blocks, void** args, hipStream_t s, uint32_t threads) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
-    return hipLaunchKernel(fn, dim3(blocks), dim3(256), args, 0, s);
-  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(256), args, 0, s);
+    return hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
 }
 
 // Zero a range of 32-bit words with a kernel (no memset node, so the sequence

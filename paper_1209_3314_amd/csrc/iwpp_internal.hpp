@@ -22,7 +22,10 @@ struct MrJob {
   int32_t h, w;
   int32_t tiles_y, tiles_x;
   uint32_t tile_base;  // first global tile id of this image
-  uint32_t pad;
+  // 0 for reconstruction by dilation; all ones for reconstruction by
+  // erosion, computed as the dilation of the complemented images (every
+  // image byte is complemented as it is loaded and stored).
+  uint32_t inv;
 };
 
 // Reconstruction launch arguments (device pointers, scratch owned by the context).
@@ -36,6 +39,10 @@ struct MrArgs {
   uint32_t list_cap;         // capacity of each round's tile list (<= ntiles)
   int32_t max_sweeps;        // sweep iterations per propagation visit before re-listing
   int32_t seed_sweeps;       // sweep iterations per tile in the seed pass
+  uint32_t seed_only;        // nonzero: stop after the seed pass (round 0)
+  uint32_t seed_strip;       // seed pass: tiles per strip (0 = automatic)
+  uint32_t stage_depth;      // work-list items staged per wave before a flush (0 = the LDS maximum)
+  uint32_t wg_waves;         // waves per workgroup: 4 or 8
   uint32_t* flags;           // [2][ntiles] tile on the round's list, per round parity
   uint32_t* lists;           // [2][8 shards][ntiles] tile lists per round parity
   uint32_t* unsettled;       // [ntiles] the tile's last visit stopped at the sweep cap
@@ -78,6 +85,8 @@ struct EdtArgs {
   uint32_t* marks;            // [2][ntiles][32] that visit's last-round change mask, one word per tile row
   uint32_t* counts;           // [3 round slots][8 shards][64] list fill levels (256 B apart)
   uint32_t* ovf;              // never set: a list holds each tile once
+  uint32_t stage_depth;       // work-list items staged per wave before a flush (0 = the LDS maximum)
+  uint32_t wg_waves;          // waves per workgroup of the rounds kernel: 4 or 8
   GridBarrier* bar;
   unsigned long long* stats;
   unsigned long long* clock;  // [kClockWords] round timeline (see kClockWords)
@@ -131,6 +140,6 @@ uint32_t persistent_grid(const void* fn, int per_cu, int cus, int max_per_cu = 4
 // captured into a graph.  Inside a graph, residency then rests on the grid
 // fitting the device when the graph runs alone; a grid that does not fit makes
 // the grid barrier time out and report an error instead of waiting forever.
-hipError_t launch_persistent(const void* fn, uint32_t blocks, void** args, hipStream_t s);
+hipError_t launch_persistent(const void* fn, uint32_t blocks, void** args, hipStream_t s, uint32_t threads = 256);
 
 }  // namespace iwpp

@@ -100,9 +100,13 @@ int32_t build_plan(iwpp_ctx* ctx, const iwpp_job* jobs, int32_t n, const char* w
 int32_t upload_tables(iwpp_ctx* ctx, const Plan& plan, uint8_t* tables, hipStream_t st, bool sync);
 // Serialise the plan's job tables into `host` (plan.table_bytes bytes).
 void pack_tables(const Plan& plan, uint8_t* host);
-// Launch the kernels of one group on `st`; `first` also clears the statistics.
+// Launch the kernels of one group on `st`; `first` also clears the statistics;
+// `seed_only` stops a reconstruction group after its seed pass.
 int32_t launch_group(iwpp_ctx* ctx, const Group& g, uint8_t* scratch, uint8_t* fixed, uint8_t* tables, hipStream_t st,
-                     bool first, iwpp::Recorder* rec);
+                     bool first, iwpp::Recorder* rec, bool seed_only = false);
+// Grow the context's scratch to at least `bytes` (waits for the device first
+// if a smaller buffer must be freed).
+int32_t ensure_scratch(iwpp_ctx* ctx, size_t bytes);
 // Sum the sharded statistics words copied from a fixed area.
 // (The round timeline is read by iwpp_round_times.)
 void fold_stats(const unsigned long long* shards, int op, iwpp_stats* out);

@@ -14,7 +14,10 @@
 // without a host round trip while later arrivals still join the batch after,
 // and uploads, computation and downloads of successive batches overlap.
 // Batches share the context's fixed area and one scratch buffer: they run one
-// after another in stream order.
+// after another in stream order.  A batch runs as one launch sequence per
+// (operation, connectivity) group; each group's jobs are downloaded and
+// completed as soon as that group's kernels end, so a small reconstruction
+// does not wait for a large distance transform launched after it.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
@@ -96,7 +99,7 @@ size_t job_buffer_bytes(const iwpp_job& j) {
   const size_t np = (size_t)j.height * (size_t)j.width;
   // recon: mask | marker (the output is written in place over the marker copy)
   // EDT: binary | sqdist | nearest
-  return j.op == IWPP_OP_RECON ? 2 * align256(np) : align256(np) + 2 * align256(4 * np);
+  return j.op != IWPP_OP_EDT ? 2 * align256(np) : align256(np) + 2 * align256(4 * np);
 }
 
 struct SJob {
@@ -110,14 +113,22 @@ struct SJob {
   hipEvent_t ready = nullptr; // recorded on the caller's stream at submit
 };
 
-struct Batch {
+// The jobs of one (operation, connectivity) group of a batch.
+struct Part {
   std::vector<uint64_t> tickets;
-  hipEvent_t done = nullptr, down = nullptr;
+  hipEvent_t done = nullptr;  // the group's kernels (and its statistics copy) ended
+  hipEvent_t down = nullptr;  // its outputs are on the host
+};
+
+struct Batch {
+  std::vector<Part> parts;
+  size_t next = 0;  // first part not yet complete
   int slot = -1;
-  size_t scratch = 0;
+  bool failed = false;  // the launch sequence could not be enqueued
 };
 
 constexpr int kSlots = 4;             // pinned table/statistics slots = batches in flight at most
+constexpr int kMaxGroups = 4;         // (operation, connectivity) groups of a plan
 constexpr int kMaxComputingBatches = 2;  // batches queued or running on the compute stream
 constexpr size_t kStatWords = iwpp::kStatShards * iwpp::kStatFields;
 
@@ -170,8 +181,11 @@ struct iwpp_server {
     if (e) event_pool.push_back(e);
   }
   uint8_t* slot_tables(int s) { return pinned + (size_t)s * slot_bytes; }
-  unsigned long long* slot_stats(int s) {
-    return reinterpret_cast<unsigned long long*>(pinned + (size_t)s * slot_bytes + table_cap);
+  // Statistics snapshot after group g of the batch in slot s (cumulative over
+  // the batch's groups 0..g).
+  unsigned long long* slot_stats(int s, int g) {
+    return reinterpret_cast<unsigned long long*>(pinned + (size_t)s * slot_bytes + table_cap +
+                                                 (size_t)g * align256(kStatWords * 8));
   }
 
   void set_error(const std::string& m) {
@@ -179,51 +193,57 @@ struct iwpp_server {
     if (error.empty()) error = m;
   }
 
-  // Finish the oldest batches whose downloads are complete.
+  // Finish, in launch order, the batch parts whose downloads are complete.
   bool complete() {
     bool progress = false;
     while (!inflight.empty()) {
       Batch& b = inflight.front();
-      const hipError_t q = hipEventQuery(b.down);
-      if (q == hipErrorNotReady) break;
-      const int64_t now = mono_ns();
-      bool ok = q == hipSuccess;
-      if (!ok) {
-        (void)hipGetLastError();
-        broken = true;
-        set_error("serving: device error in a batch");
-      } else {
-        iwpp_stats s;
-        iwpp::rt::fold_stats(slot_stats(b.slot), 3, &s);
-        if (s.status != IWPP_OK) {
-          ok = false;
-          set_error("serving: a batch hit a kernel safety limit");
+      while (b.next < b.parts.size()) {
+        Part& p = b.parts[b.next];
+        const hipError_t q = b.failed ? hipSuccess : hipEventQuery(p.down);
+        if (q == hipErrorNotReady) break;
+        const int64_t now = mono_ns();
+        bool ok = q == hipSuccess && !b.failed;
+        if (q != hipSuccess) {
+          (void)hipGetLastError();
+          broken = true;
+          set_error("serving: device error in a batch");
+        } else if (ok) {
+          iwpp_stats s;
+          iwpp::rt::fold_stats(slot_stats(b.slot, (int)b.next), 3, &s);
+          if (s.status != IWPP_OK) {
+            ok = false;
+            set_error("serving: a batch hit a kernel safety limit");
+          }
         }
-      }
-      {
-        std::lock_guard<std::mutex> g(mu);
-        for (uint64_t t : b.tickets) {
-          SJob& j = jobs[t];
-          j.state = ok ? IWPP_JOB_DONE : IWPP_JOB_FAILED;
-          j.done_ns = now;
-          put_event(j.up);
-          j.up = nullptr;
-          if (j.ready) ready_pool.push_back(j.ready);
-          j.ready = nullptr;
-          if (j.bytes) arena.release(j.off, j.bytes);
-          if (ok)
-            st.completed++;
-          else
-            st.failed++;
-          st.admitted_now--;
+        {
+          std::lock_guard<std::mutex> g(mu);
+          for (uint64_t t : p.tickets) {
+            SJob& j = jobs[t];
+            j.state = ok ? IWPP_JOB_DONE : IWPP_JOB_FAILED;
+            j.done_ns = now;
+            put_event(j.up);
+            j.up = nullptr;
+            if (j.ready) ready_pool.push_back(j.ready);
+            j.ready = nullptr;
+            if (j.bytes) arena.release(j.off, j.bytes);
+            if (ok)
+              st.completed++;
+            else
+              st.failed++;
+            st.admitted_now--;
+          }
         }
+        put_event(p.done);
+        put_event(p.down);
+        p.done = p.down = nullptr;
+        b.next++;
+        progress = true;
+        cv.notify_all();
       }
+      if (b.next < b.parts.size()) break;
       slot_busy[b.slot] = false;
-      put_event(b.done);
-      put_event(b.down);
       inflight.pop_front();
-      progress = true;
-      cv.notify_all();
     }
     return progress;
   }
@@ -276,7 +296,7 @@ struct iwpp_server {
       iwpp_job d = j->host;
       // The copies wait for the caller's work queued before the submit.
       bool ok = hipStreamWaitEvent(h2d, j->ready, 0) == hipSuccess;
-      if (d.op == IWPP_OP_RECON) {
+      if (d.op != IWPP_OP_EDT) {
         uint8_t* mask = base;
         uint8_t* marker = base + align256(np);  // overwritten by the result
         d.in1 = mask;
@@ -322,9 +342,11 @@ struct iwpp_server {
   // Launch the admitted jobs as one batch when the compute stream has room.
   bool launch() {
     if (admitted.empty() || broken) return false;
-    int computing = 0;
+    int computing = 0;  // batches whose last group has not finished computing
     for (const Batch& q : inflight)
-      if (hipEventQuery(q.done) == hipErrorNotReady) computing++;
+      if (!q.failed && !q.parts.empty() && q.parts.back().done &&
+          hipEventQuery(q.parts.back().done) == hipErrorNotReady)
+        computing++;
     if (computing >= kMaxComputingBatches) return false;
     int slot = -1;
     for (int s = 0; s < kSlots; ++s)
@@ -374,16 +396,25 @@ struct iwpp_server {
     }
     tk.resize(n);
     Batch b;
-    b.tickets = tk;
     b.slot = slot;
-    b.done = get_event();
-    b.down = get_event();
+    // One part per plan group, holding that group's tickets in plan order
+    // (build_plan keeps the jobs' order inside a group).
+    for (const iwpp::rt::Group& g : plan.groups) {
+      Part p;
+      for (size_t i = 0; i < n; ++i)
+        if ((dj[i].op == IWPP_OP_EDT ? IWPP_OP_EDT : IWPP_OP_RECON) == g.op && dj[i].conn == g.conn)
+          p.tickets.push_back(tk[i]);
+      p.done = get_event();
+      p.down = get_event();
+      b.parts.push_back(std::move(p));
+    }
     const size_t sb = align256(plan.scratch_bytes);
     uint8_t* tables = scratch + sb;
     iwpp::rt::pack_tables(plan, slot_tables(slot));
     iwpp::Recorder off;
-    bool ok = b.done && b.down;
-    if (opt.resident) {
+    bool ok = (int)b.parts.size() <= kMaxGroups;
+    for (const Part& p : b.parts) ok = ok && p.done && p.down;
+    if (ok && opt.resident) {
       // A resident job's buffers are the caller's: its batch waits for the
       // work the caller queued on its stream before the submit (inputs being
       // written, earlier users of the output memory).
@@ -392,24 +423,21 @@ struct iwpp_server {
     }
     if (ok && plan.table_bytes)
       ok = hipMemcpyAsync(tables, slot_tables(slot), plan.table_bytes, hipMemcpyHostToDevice, comp) == hipSuccess;
-    bool first = true;
-    for (const iwpp::rt::Group& g : plan.groups) {
+    for (size_t gi = 0; gi < plan.groups.size() && ok; ++gi) {
+      Part& p = b.parts[gi];
+      ok = iwpp::rt::launch_group(&wctx, plan.groups[gi], scratch, wctx.fixed, tables, comp, gi == 0, &off) == IWPP_OK;
+      ok = ok &&
+           hipMemcpyAsync(slot_stats(slot, (int)gi), wctx.fixed + iwpp::rt::kOffStats, kStatWords * 8,
+                          hipMemcpyDeviceToHost, comp) == hipSuccess &&
+           hipEventRecord(p.done, comp) == hipSuccess && hipStreamWaitEvent(d2h, p.done, 0) == hipSuccess;
       if (!ok) break;
-      ok = iwpp::rt::launch_group(&wctx, g, scratch, wctx.fixed, tables, comp, first, &off) == IWPP_OK;
-      first = false;
-    }
-    ok = ok &&
-         hipMemcpyAsync(slot_stats(slot), wctx.fixed + iwpp::rt::kOffStats, kStatWords * 8, hipMemcpyDeviceToHost,
-                        comp) == hipSuccess &&
-         hipEventRecord(b.done, comp) == hipSuccess && hipStreamWaitEvent(d2h, b.done, 0) == hipSuccess;
-    if (ok) {
       std::lock_guard<std::mutex> g(mu);
-      for (uint64_t t : tk) {
+      for (uint64_t t : p.tickets) {
         SJob& j = jobs[t];
         const size_t np = (size_t)j.host.height * (size_t)j.host.width;
         if (opt.resident) {
           // outputs are the caller's device buffers
-        } else if (j.host.op == IWPP_OP_RECON) {
+        } else if (j.host.op != IWPP_OP_EDT) {
           ok = ok && hipMemcpyAsync(j.host.out0, j.dev.out0, np, hipMemcpyDeviceToHost, d2h) == hipSuccess;
         } else {
           ok = ok && hipMemcpyAsync(j.host.out0, j.dev.out0, 4 * np, hipMemcpyDeviceToHost, d2h) == hipSuccess &&
@@ -417,15 +445,19 @@ struct iwpp_server {
         }
         j.state = IWPP_JOB_RUNNING;
       }
+      ok = ok && hipEventRecord(p.down, d2h) == hipSuccess;
+    }
+    if (ok) {
+      std::lock_guard<std::mutex> g(mu);
       st.batches++;
       if ((int64_t)n > st.max_batch_jobs) st.max_batch_jobs = (int64_t)n;
     }
-    ok = ok && hipEventRecord(b.down, d2h) == hipSuccess;
     for (size_t i = 0; i < n; ++i) admitted.pop_front();
     slot_busy[slot] = true;
     if (!ok) {
       (void)hipGetLastError();
       broken = true;
+      b.failed = true;
       set_error(std::string("serving: batch launch failed: ") + wctx.err);
       // Wait for what was enqueued, then let complete() fail the batch.
       (void)hipStreamSynchronize(comp);
@@ -524,7 +556,7 @@ int32_t iwpp_server_start(iwpp_ctx* ctx, const iwpp_server_options* opt, iwpp_se
   s->table_cap = align256((size_t)o.max_batch * (sizeof(iwpp::EdtJob) > sizeof(iwpp::MrJob) ? sizeof(iwpp::EdtJob)
                                                                                                  : sizeof(iwpp::MrJob)) +
                           4 * 256);
-  s->slot_bytes = s->table_cap + align256(kStatWords * 8);
+  s->slot_bytes = s->table_cap + kMaxGroups * align256(kStatWords * 8);
   void* a = nullptr;
   void* sc = nullptr;
   void* pin = nullptr;
@@ -564,10 +596,11 @@ int32_t iwpp_server_submit(iwpp_server* s, const iwpp_job* job, int64_t arrival_
   iwpp_ctx* ctx = s->ctx;
   if (!job || !ticket) return fail(ctx, IWPP_EINVAL, "server_submit: NULL argument");
   const iwpp_job& j = *job;
-  if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_EDT) return fail(ctx, IWPP_EINVAL, "server_submit: op must be RECON or EDT");
+  if (j.op != IWPP_OP_RECON && j.op != IWPP_OP_RECON_ERODE && j.op != IWPP_OP_EDT)
+    return fail(ctx, IWPP_EINVAL, "server_submit: op must be RECON, RECON_ERODE or EDT");
   if (j.conn != 4 && j.conn != 8) return fail(ctx, IWPP_EINVAL, "server_submit: conn must be 4 or 8");
   if (j.height < 1 || j.width < 1) return fail(ctx, IWPP_EINVAL, "server_submit: height and width must be >= 1");
-  if (j.op == IWPP_OP_RECON && (!j.in0 || !j.in1 || !j.out0 || j.out1))
+  if (j.op != IWPP_OP_EDT && (!j.in0 || !j.in1 || !j.out0 || j.out1))
     return fail(ctx, IWPP_EINVAL, "server_submit: reconstruction needs in0, in1, out0 and no out1");
   if (j.op == IWPP_OP_EDT && (!j.in0 || j.in1 || !j.out0 || !j.out1))
     return fail(ctx, IWPP_EINVAL, "server_submit: EDT needs in0, out0, out1 and no in1");

@@ -46,7 +46,8 @@ def test_binding_rejects_bad_tensors_before_the_library():
 
 # C struct name in include/iwpp.h -> ctypes mirror in the binding
 _MIRRORS = {"iwpp_options": "Options", "iwpp_stats": "Stats", "iwpp_kernel_time": "KernelTime",
-            "iwpp_job": "Job", "iwpp_server_options": "ServerOptions", "iwpp_server_stats": "ServerStats"}
+            "iwpp_job": "Job", "iwpp_server_options": "ServerOptions", "iwpp_server_stats": "ServerStats",
+            "iwpp_queue_options": "QueueOptions"}
 
 
 def test_struct_layouts_match_the_header(tmp_path):

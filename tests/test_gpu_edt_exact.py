@@ -1,0 +1,77 @@
+"""The exact EDT (separable lower-envelope method) on the GPU: squared
+distances equal the oracle's exact EDT (itself pinned to scipy and to brute
+force), and every nearest index names a feature at exactly that distance."""
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from paper_1209_3314_amd import synth
+from tests.gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch, iw = require_gpu()
+    ctx = iw.Context(0)
+    yield torch, iw, ctx
+    ctx.close()
+
+
+def run(env, B):
+    torch, iw, ctx = env
+    d = torch.device("cuda", 0)
+    sq, nr = ctx.edt_exact(torch.from_numpy(B).to(d))
+    torch.cuda.synchronize()
+    return sq.cpu().numpy(), nr.cpu().numpy()
+
+
+def check(B, sq, nr):
+    h, w = B.shape
+    ex = oracle.edt_exact_sep(B)
+    assert np.array_equal(sq.astype(np.int64), ex)
+    if not (B == 0).any():
+        assert (nr == -1).all()
+        return
+    assert (nr >= 0).all() and (nr < h * w).all()
+    fy, fx = nr // w, nr % w
+    assert (B.reshape(-1)[nr.reshape(-1)] == 0).all()  # a feature
+    yy, xx = np.mgrid[0:h, 0:w]
+    assert np.array_equal((yy - fy) ** 2 + (xx - fx) ** 2, sq)  # at exactly that distance
+
+
+@pytest.mark.parametrize("h,w,cov,seed", [(1, 1, 0.0, 1), (1, 1, 1.0, 2), (1, 500, 0.01, 3), (500, 1, 0.01, 4),
+                                          (129, 257, 0.3, 5), (300, 400, 0.0, 6), (300, 400, 0.002, 7),
+                                          (1000, 700, 0.3, 8)])
+def test_exact_edt(env, h, w, cov, seed):
+    B = synth.edt_input(h, w, seed=seed, coverage=cov) if cov < 1.0 else np.zeros((h, w), np.uint8)
+    announce("edt exact", h, w, cov)
+    check(B, *run(env, B))
+
+
+def test_exact_edt_single_feature_far_corner(env):
+    """One feature: distances up to the far corner, and the envelope holds a
+    single parabola in most rows."""
+    B = np.ones((777, 1111), np.uint8)
+    B[776, 0] = 0
+    announce("edt exact single feature")
+    check(B, *run(env, B))
+
+
+def test_exact_edt_4k_workload(env):
+    """The 4096 x 4096 nucleus-like workload: exact everywhere, including the
+    pixels where the propagation approximation is not."""
+    B = synth.workload_edt_4k()
+    announce("edt exact 4096^2")
+    sq, nr = run(env, B)
+    check(B, sq, nr)
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(1, 40), st.integers(1, 40), st.floats(0.0, 0.5), st.integers(0, 2**31 - 1))
+def test_exact_edt_random_small(env, h, w, p, seed):
+    rng = np.random.default_rng(seed)
+    B = (rng.random((h, w)) >= p).astype(np.uint8)
+    check(B, *run(env, B))
