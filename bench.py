@@ -35,6 +35,12 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpixel/s morph-recon & EDT (bit-exact) + batched p50/p99 tile latency vs plain"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# The paper's own end-to-end speedups (context only: other hardware, other
+# images, several devices).
+PAPER_CONTEXT = {
+    "reconstruction": "50x over one CPU core, 96K x 96K image, 3 NVIDIA M2090 GPUs + 12 Xeon X5660 cores (Sec. 5.3)",
+    "edt": "85.6x over one CPU core, 64K x 64K image, same machine (Sec. 5.3)",
+}
 CSRC = os.path.join(ROOT, "paper_1209_3314_amd", "csrc")
 
 
@@ -91,7 +97,7 @@ def _oracle_tile(args):
     return bool(np.array_equal(s, got[0]) and np.array_equal(n, got[1]))
 
 
-SERVE_POOL = 64
+SERVE_POOL = 512
 
 
 def _gen_serve(i):
@@ -174,7 +180,8 @@ def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dic
                 "peak_gib": round(st["peak_bytes"] / 2**30, 2), "failed": st["failed"], "equal_to_plain_calls": exact}
 
     res = {"workload": f"{SERVE_POOL}-tile pool: square sides lognormal(median 1024, sigma 0.7) clipped [256, 8192], "
-                       "70% reconstruction / 30% EDT, conn 8; Poisson arrivals; host buffers pinned; 64 GiB budget",
+                       "70% reconstruction / 30% EDT, conn 8; Poisson arrivals; host buffers pinned; 64 GiB budget; "
+                       "every request uploads its inputs to fresh device memory, so pool reuse gives no cache reuse",
            "pool_mpix": round(sum(npx) / 1e6, 1), "rates": []}
     for rate in rates:
         arr = synth.serve_arrivals(rate, seconds, SERVE_POOL)
@@ -191,6 +198,14 @@ def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dic
             cap[mode] = summary(arr, *run(mb, arr))
             log(f"serve burst {mode}: {cap[mode]}")
         cap["throughput_batched_over_plain"] = round(cap["batched"]["mpix_s"] / max(cap["plain"]["mpix_s"], 1e-9), 3)
+        # The host-buffer burst moves every input up and every output down
+        # over PCIe: its bytes per second beside what plain pinned copies reach.
+        up = sum(npx[i] * (2 if specs[i]["op"] == "mr" else 1) for _, i in arr)
+        down = sum(npx[i] * (1 if specs[i]["op"] == "mr" else 8) for _, i in arr)
+        span_b = sum(npx[i] for _, i in arr) / (cap["batched"]["mpix_s"] * 1e6)
+        cap["pcie"] = {"bytes_up": up, "bytes_down": down, "batched_gb_s": round((up + down) / span_b / 1e9, 2),
+                       "pinned_copy_gb_s": pinned_copy_rates(torch)}
+        log(f"serve burst PCIe: {cap['pcie']}")
         res["capacity"] = cap
         # Device-resident serving: the pool's inputs uploaded once, every request with
         # device outputs of its own, no copies in the loop.
@@ -234,8 +249,121 @@ def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dic
     return res
 
 
+def slide_leg(ctx, torch, np) -> dict:
+    """A whole slide in one call: reconstruction by dilation, 8-connected, of
+    a 65536 x 65600 image (4.3 G pixels, above 2^32), generated block-wise
+    (32 x 32 blocks of uniform level plus row and column ripples; marker =
+    mask - 40 except in 0.2% of the blocks).  Inputs resident in HBM; device
+    time of one call after one warm-up.  Bit-exactness at this size is checked
+    by the GPU tests against the oracle (about 100 s of CPU), not here."""
+    from paper_1209_3314_amd import synth
+
+    h, w = 65536, 65600
+    t = time.time()
+    J, I = synth.slide_mr_inputs(h, w, seed=11)
+    gen_s = time.time() - t
+    dev = torch.device("cuda", 0)
+    Id = torch.from_numpy(I).to(dev)
+    Jd = torch.from_numpy(J).to(dev)
+    del J, I
+    out = torch.empty_like(Id)
+    ctx.morph_recon(Jd, Id, 8, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.morph_recon(Jd, Id, 8, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st = ctx.stats()
+    del Id, Jd, out
+    torch.cuda.empty_cache()
+    res = {"workload": f"reconstruction by dilation, conn 8, {h}x{w} whole slide (block field, seed 11)",
+           "pixels": h * w, "ms": round(ms, 2), "mpix_s": round(h * w / (ms * 1e-3) / 1e6, 1),
+           "status": st["status"], "rounds": st["rounds"], "tile_visits": st["items"],
+           "input_generation_s": round(gen_s, 1)}
+    log(f"slide: {res}")
+    return res
+
+
+def pinned_copy_rates(torch) -> dict:
+    """Host<->device rates of plain 256 MiB copies from and to pinned memory,
+    each direction alone and both at once (GB/s, best of 3)."""
+    n = 256 << 20
+    h1 = torch.empty(n, dtype=torch.uint8).pin_memory()
+    h2 = torch.empty(n, dtype=torch.uint8).pin_memory()
+    d1 = torch.empty(n, dtype=torch.uint8, device="cuda")
+    d2 = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def best(fn):
+        b = float("inf")
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            b = min(b, time.perf_counter() - t)
+        return b
+
+    up = best(lambda: d1.copy_(h1, non_blocking=True))
+    down = best(lambda: h2.copy_(d2, non_blocking=True))
+
+    def both():
+        with torch.cuda.stream(s1):
+            d1.copy_(h1, non_blocking=True)
+        with torch.cuda.stream(s2):
+            h2.copy_(d2, non_blocking=True)
+
+    bi = best(both)
+    return {"h2d": round(n / up / 1e9, 1), "d2h": round(n / down / 1e9, 1), "both": round(2 * n / bi / 1e9, 1)}
+
+
 def pool_workers() -> int:
-    return max(1, min(16, len(os.sched_getaffinity(0))))
+    return max(1, min(16, len(os.sched_getaffinity(0)) - 1))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_child(conn, core: int, reps: int) -> None:
+    """The CPU baseline: the oracle (single-threaded C) over one full step,
+    pinned to one core, `reps` times.  Sends the run times, the work counts
+    and digests of the outputs (the parent compares the GPU's outputs with
+    them)."""
+    import hashlib
+
+    import numpy as np
+
+    import oracle
+    from paper_1209_3314_amd import synth
+
+    try:
+        os.sched_setaffinity(0, {core})
+        Jm, Im = synth.workload_mr_16k()
+        Be = synth.workload_edt_4k()
+        times = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            r8, s8 = oracle.mr_fh(Jm, Im, 8, return_stats=True)
+            r4, s4 = oracle.mr_fh(Jm, Im, 4, return_stats=True)
+            es, en, se = oracle.edt_rounds(Be, 8, return_stats=True)
+            times.append(time.perf_counter() - t)
+        dig = lambda a: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+        conn.send({"times": times, "q_ref": {"mr16k_conn8": s8["pops"], "mr16k_conn4": s4["pops"],
+                                             "edt4k_conn8": se["items"]},
+                   "digests": [dig(r8), dig(r4), dig(es), dig(en)]})
+    except Exception as e:  # reported by the parent
+        conn.send({"error": repr(e)})
+    conn.close()
 
 
 def batch_leg(ctx, torch, np, pool, gen, ntiles: int, check: bool) -> dict:
@@ -318,6 +446,25 @@ def batch_leg(ctx, torch, np, pool, gen, ntiles: int, check: bool) -> dict:
     gstats = g.stats()
     g.close()
     ctx.profile_read()
+    # Tuned: the autotuner's batch grid on this batch (tune_jobs checks every
+    # candidate's outputs against the default options' outputs), then the
+    # batch and a graph captured under the chosen options.
+    from paper_1209_3314_amd import tune
+
+    t = time.time()
+    saved = dict(ctx.options)
+    best, _, _ = tune.tune_jobs(ctx, jobs, reps=2)
+    tune_s = time.time() - t
+    ctx.set_options(**best)
+    tbatch_ms, tbatch_same = timed(lambda: ctx.run_batch(jobs))
+    gt = ctx.batch_graph(jobs)
+    gt.launch()
+    torch.cuda.synchronize()
+    tgraph_ms, tgraph_same = timed(lambda: gt.launch())
+    tgstats = gt.stats()
+    gt.close()
+    ctx.set_options(**saved)
+    ctx.profile_read()
     plain_ms = float(done_plain[-1])
     res = {
         "tiles": ntiles, "pixels": px, "workload": "256-tile mixed batch: sides U[512,4096], even tiles reconstruction "
@@ -334,6 +481,11 @@ def batch_leg(ctx, torch, np, pool, gen, ntiles: int, check: bool) -> dict:
                           "p99": round(float(np.percentile(np.diff(done_plain, prepend=0.0), 99)), 3)},
         "batch_equals_plain": bool(batch_same), "graph_equals_plain": bool(graph_same),
         "batch_status": bstats["status"], "graph_status": gstats["status"],
+        "tuned": {"options": {k: v for k, v in best.items() if v}, "tuning_s": round(tune_s, 1),
+                  "batch_ms": round(tbatch_ms, 3), "graph_ms": round(tgraph_ms, 3),
+                  "speedup_batch": round(plain_ms / tbatch_ms, 3), "speedup_graph": round(plain_ms / tgraph_ms, 3),
+                  "batch_equals_plain": bool(tbatch_same), "graph_equals_plain": bool(tgraph_same),
+                  "graph_status": tgstats["status"]},
         "bit_exact": None, "cpu_baseline": None,
     }
     if check:
@@ -359,8 +511,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-tile batched leg")
     ap.add_argument("--batch-tiles", type=int, default=256, help="tiles in the batched leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-slide", action="store_true", help="skip the whole-slide reconstruction leg")
     ap.add_argument("--serve-rates", default="200,800,2000", help="comma-separated request rates (per second)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0, help="trace length per rate")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="trace length per rate")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs of the CPU baseline (median reported)")
     ap.add_argument("--serve-burst", type=int, default=256, help="requests of the capacity burst (0 = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (reference for rocprofv3 byte counters)")
@@ -384,6 +538,20 @@ def main():
               "shard one per GPU, one image in horizontal bands). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    # The CPU baseline runs in a child pinned to one core (the paper's
+    # single-core baseline, median of 3 runs); this process and the tile
+    # generators keep off that core.  Forked before the GPU is initialised.
+    oracle_rx = oracle_proc = None
+    cores = sorted(os.sched_getaffinity(0))
+    if not args.no_cpu_baseline:
+        from multiprocessing import Pipe, get_context
+
+        oracle_rx, tx = Pipe(duplex=False)
+        oracle_proc = get_context("fork").Process(target=_oracle_child, args=(tx, cores[0], args.cpu_reps))
+        oracle_proc.start()
+        tx.close()
+        if len(cores) > 1:
+            os.sched_setaffinity(0, set(cores[1:]))
     pool = gen = None
     if not args.no_batch:
         # Workers are forked before this process initialises the GPU; the batch
@@ -480,23 +648,35 @@ def main():
     # ---- oracle: CPU baseline + bit-exactness + work counts ----
     q_ref, cpu = {}, None
     bit_exact = None
+    edt_vs_exact = None
     if not args.no_cpu_baseline:
+        import hashlib
+
         import oracle
 
         g8, g4 = o8.cpu().numpy(), o4.cpu().numpy()
         gs, gn = sq.cpu().numpy(), nr.cpu().numpy()
-        t = time.perf_counter()
-        r8, s8 = oracle.mr_fh(Jm, Im, 8, return_stats=True)
-        r4, s4 = oracle.mr_fh(Jm, Im, 4, return_stats=True)
-        es, en, se = oracle.edt_rounds(Be, 8, return_stats=True)
-        cpu_s = time.perf_counter() - t
-        bit_exact = bool(np.array_equal(g8, r8) and np.array_equal(g4, r4) and np.array_equal(gs, es)
-                         and np.array_equal(gn, en))
-        q_ref = {"mr16k_conn8": s8["pops"], "mr16k_conn4": s4["pops"], "edt4k_conn8": se["items"]}
+        res = oracle_rx.recv()
+        oracle_proc.join()
+        if "error" in res:
+            raise RuntimeError(f"oracle child failed: {res['error']}")
+        dig = lambda a: hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+        bit_exact = [dig(g8), dig(g4), dig(gs), dig(gn)] == res["digests"]
+        q_ref = res["q_ref"]
+        cpu_s = float(np.median(res["times"]))
         cpu = {"value": round((2 * n_mr + n_edt) / cpu_s / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
                "sample": "one full step (16384^2 reconstruction conn 8 and conn 4, 4096^2 EDT conn 8), "
-                         f"{cpu_s:.1f} s single-threaded C on the host"}
-        log(f"oracle step {cpu_s:.1f}s bit_exact={bit_exact} q_ref={q_ref}")
+                         f"median of {len(res['times'])} runs pinned to one core: {cpu_s:.1f} s single-threaded C",
+               "runs_s": [round(x, 2) for x in res["times"]], "cpu_model": cpu_model(),
+               "host_cores_allowed": len(cores), "host_cpu_count": os.cpu_count()}
+        log(f"oracle step median {cpu_s:.1f}s bit_exact={bit_exact} q_ref={q_ref}")
+        # The propagation EDT against the exact EDT, on the timed output.
+        ex = oracle.edt_exact_sep(Be)
+        diff = gs.astype(np.int64) != ex
+        err = np.abs(np.sqrt(gs.astype(np.float64)) - np.sqrt(ex.astype(np.float64)))
+        edt_vs_exact = {"pixels_differing": int(diff.sum()), "fraction": float(diff.mean()),
+                        "max_distance_error_px": float(err.max()), "tolerance": {"fraction": 1e-4, "max_px": 1.0}}
+        log(f"EDT vs exact: {edt_vs_exact}")
 
     # ---- roofline of the dominant kernel ----
     dom_key = max(kernels, key=kernels.get)
@@ -527,6 +707,9 @@ def main():
                                  "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "mpix_s": round(n / (ms * 1e-3) / 1e6, 1)}
 
+    slide = None
+    if not args.no_slide:
+        slide = slide_leg(ctx, torch, np)
     batch = None
     if not args.no_batch:
         batch = batch_leg(ctx, torch, np, pool, gen, args.batch_tiles, check=not args.no_cpu_baseline)
@@ -555,7 +738,10 @@ def main():
         "per_op": op_roofline, "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
         "wall_ms_per_step": round(wall_ms / args.steps, 4),
         "work": {"q_ref": q_ref, "gpu": gpu_stats},
+        "edt_vs_exact": edt_vs_exact,
+        "paper_context": PAPER_CONTEXT,
         "batch": batch,
+        "slide": slide,
         "serve": serve,
     }
     print(json.dumps(line), flush=True)

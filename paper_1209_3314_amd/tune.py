@@ -1,15 +1,24 @@
 """Autotuner for the library's launch options.
 
-The options of ``iwpp_options`` change only speed, never results: the
-persistent grid size (workgroups of the propagation kernels, the paper's
-blocks-per-multiprocessor knob of Sec. 5.2), the sweep caps per tile visit and
-per seed-pass tile (the number of initial raster scans that Table 1 varies) and
-the work-list capacity (the global queue size of Sec. 3.2).  The tuner times a
-small grid of candidates per (operation, connectivity, size bucket) on
-synthetic inputs of that bucket, checks that every candidate's output equals
-the default options' output byte for byte, keeps the fastest, and caches the
-choice as JSON keyed by device and library version.  ``TunedContext`` applies
-the cached choice before each call.
+The options of ``iwpp_options`` change only speed, never results:
+  * ``wg_waves`` -- waves per workgroup of the persistent kernels (the
+    workgroup size; one wave holds one tile);
+  * ``stage_depth`` -- work-list items a wave stages in LDS before one global
+    atomic appends them (the depth of the paper's per-block queue);
+  * ``mr_seed_strip`` -- tiles per vertical strip of the reconstruction seed
+    pass (its tiling: each tile reads the one above it fresh);
+  * ``mr_seed_sweeps`` / ``mr_max_sweeps`` -- sweep iterations per seed-pass
+    tile and per propagation visit (the number of initial scans that Table 1
+    varies);
+  * ``persistent_blocks`` -- workgroups of the persistent kernels (the
+    paper's blocks-per-multiprocessor knob, Sec. 5.2).
+The tuner times a grid of candidates per (operation, connectivity, size
+bucket) on synthetic inputs of that bucket -- and, for the "batch" bucket, on
+a sample of the mixed 256-tile batch through ``run_batch`` -- checks that every
+candidate's output equals the default options' output byte for byte, keeps
+the fastest, and caches the choice as JSON keyed by device and library
+version.  ``TunedContext`` applies the cached choice before each call,
+``run_batch`` and ``batch_graph`` included.
 """
 from __future__ import annotations
 
@@ -20,14 +29,19 @@ import time
 
 from . import Context, _lib
 
-DEFAULTS = {"persistent_blocks": 0, "mr_max_sweeps": 0, "mr_seed_sweeps": 0, "mr_list_capacity": 0}
+DEFAULTS = {"persistent_blocks": 0, "mr_max_sweeps": 0, "mr_seed_sweeps": 0, "mr_list_capacity": 0, "wg_waves": 0,
+            "stage_depth": 0, "mr_seed_strip": 0}
 
-# Candidate grids.  0 means the library default (device-filling grid, default
-# sweep caps).
+# Candidate grids.  0 means the library default (device-filling grid, four
+# waves per workgroup, the deepest LDS stage, automatic strips, default sweep
+# caps).
 GRID = {
-    "recon": [{"persistent_blocks": pb, "mr_max_sweeps": ms, "mr_seed_sweeps": ss}
-              for pb in (0, 512, 768) for ms in (1, 0, 4) for ss in (0, 1, 2, 4)],
-    "edt": [{"persistent_blocks": pb} for pb in (0, 128, 256, 512)],
+    "recon": [{"wg_waves": wg, "stage_depth": sd, "mr_seed_strip": sp, "mr_max_sweeps": ms, "mr_seed_sweeps": ss}
+              for wg in (0, 8) for sd in (0, 16) for sp in (0, 4, 16) for ms in (0, 1) for ss in (0, 2)],
+    "edt": [{"wg_waves": wg, "stage_depth": sd, "persistent_blocks": pb}
+            for wg in (0, 8) for sd in (0, 16) for pb in (0, 512)],
+    "batch": [{"wg_waves": wg, "stage_depth": sd, "mr_max_sweeps": ms, "persistent_blocks": pb}
+              for wg in (0, 8) for sd in (0, 16) for ms in (0, 1) for pb in (0, 512)],
 }
 
 
@@ -120,14 +134,81 @@ def _timed(fn, reps: int) -> float:
     return best
 
 
+def batch_pixels(jobs: list) -> int:
+    """Pixels of a batch (the size of its "batch" bucket)."""
+    n = 0
+    for j in jobs:
+        t = j["mask"] if j["op"] in ("recon", "erode") else j["binary"]
+        n += t.numel()
+    return n
+
+
+def _job_outputs(jobs: list) -> list:
+    return [t for j in jobs for t in ((j["out"],) if j["op"] in ("recon", "erode") else (j["sqdist"], j["nearest"]))]
+
+
+def tune_jobs(ctx: Context, jobs: list, reps: int = 3) -> tuple:
+    """Time every candidate of GRID["batch"] on ``ctx.run_batch(jobs)``.
+    Returns (best options, best ms, default ms); raises if a candidate's
+    outputs differ from the default options' outputs."""
+    import torch
+
+    saved = dict(ctx.options)
+    outs = _job_outputs(jobs)
+    fn = lambda: ctx.run_batch(jobs)
+    try:
+        ctx.set_options(**DEFAULTS)
+        default_ms = _timed(fn, reps)
+        ref = [o.clone() for o in outs]
+        best, best_ms = dict(DEFAULTS), default_ms
+        for cand in GRID["batch"]:
+            opts = dict(DEFAULTS, **cand)
+            ctx.set_options(**opts)
+            ms = _timed(fn, reps)
+            if not all(torch.equal(o, r) for o, r in zip(outs, ref)):
+                raise RuntimeError(f"tuning candidate {opts} changed a batch result")
+            if ms < best_ms:
+                best, best_ms = opts, ms
+        return best, best_ms, default_ms
+    finally:
+        ctx.set_options(**saved)
+
+
+def _batch_sample(pixels: int, device) -> list:
+    """Tiles of the mixed batch (synth.batch_tile_spec) in order until they
+    hold at least `pixels` pixels, as device jobs with outputs."""
+    import torch
+
+    from . import synth
+
+    jobs, n, i = [], 0, 0
+    while n < pixels:
+        spec = synth.batch_tile_spec(i)
+        x = synth.tile_inputs(spec)
+        h, w = spec["h"], spec["w"]
+        if spec["op"] == "mr":
+            jobs.append({"op": "recon", "conn": spec["conn"], "marker": torch.from_numpy(x[0]).to(device),
+                         "mask": torch.from_numpy(x[1]).to(device),
+                         "out": torch.empty((h, w), dtype=torch.uint8, device=device)})
+        else:
+            jobs.append({"op": "edt", "conn": spec["conn"], "binary": torch.from_numpy(x).to(device),
+                         "sqdist": torch.empty((h, w), dtype=torch.int32, device=device),
+                         "nearest": torch.empty((h, w), dtype=torch.int32, device=device)})
+        n += h * w
+        i += 1
+    return jobs
+
+
 def tune_bucket(ctx: Context, op: str, conn: int, key: str, reps: int = 3, seed: int = 0) -> tuple:
     """Time every candidate of GRID[op] on a synthetic image of bucket `key`.
     Returns (best options, best ms, default ms).  Raises if any candidate's
     output differs from the default options' output."""
     import torch
 
-    h, w = bucket_side(key)
     dev = torch.device("cuda", ctx.device)
+    if op == "batch":
+        return tune_jobs(ctx, _batch_sample(1 << int(key.rsplit("2^", 1)[1]) - 1, dev), reps)
+    h, w = bucket_side(key)
     saved = dict(ctx.options)
     x = _make_inputs(op, h, w, seed)
     if op == "recon":
@@ -203,3 +284,16 @@ class TunedContext(Context):
     def edt(self, binary, conn: int = 8, out=None):
         self._apply("edt", conn, binary.numel())
         return super().edt(binary, conn, out)
+
+    def morph_recon_erode(self, marker, mask, conn: int = 8, out=None):
+        self._apply("recon", conn, mask.numel())
+        return super().morph_recon_erode(marker, mask, conn, out)
+
+    def run_batch(self, jobs: list) -> None:
+        self._apply("batch", 0, batch_pixels(jobs))
+        return super().run_batch(jobs)
+
+    def batch_graph(self, jobs: list):
+        # the options are read when the graph is captured
+        self._apply("batch", 0, batch_pixels(jobs))
+        return super().batch_graph(jobs)

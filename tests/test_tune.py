@@ -69,3 +69,46 @@ def test_tuning_never_changes_results(tmp_path):
     es, en = oracle.edt_rounds(B, 8)
     assert np.array_equal(s.cpu().numpy(), es) and np.array_equal(n.cpu().numpy(), en)
     ctx.close()
+
+
+def test_batch_bucket_and_grid():
+    assert tune.bucket("batch", 0, 1 << 20) == "batch/0/2^20"
+    assert "batch" in tune.GRID and len(tune.GRID["batch"]) >= 8
+    # every knob the survey names is tuned: workgroup size, LDS stage depth, seed tiling
+    knobs = set().union(*[set(c) for c in tune.GRID["recon"]])
+    assert {"wg_waves", "stage_depth", "mr_seed_strip"} <= knobs
+
+
+@pytest.mark.gpu
+def test_tuned_batch_never_changes_results(tmp_path):
+    from tests.gpu_util import announce, require_gpu
+
+    torch, iw = require_gpu()
+    import oracle
+    from paper_1209_3314_amd import synth
+
+    announce("autotune batch bucket")
+    pixels = 1 << 22
+    cache = tune.autotune([("batch", 0, pixels)], cache_path=str(tmp_path / "t.json"), reps=1)
+    key = tune.bucket("batch", 0, pixels)
+    assert cache.get(key) is not None
+    d = torch.device("cuda", 0)
+    jobs = tune._batch_sample(pixels // 2, d)
+    ctx = tune.TunedContext(0, cache=cache)
+    cache.put(tune.bucket("batch", 0, tune.batch_pixels(jobs)), cache.get(key), 1.0, 1.0)
+    ctx.run_batch(jobs)
+    torch.cuda.synchronize()
+    for i, j in enumerate(jobs):
+        spec = synth.batch_tile_spec(i)
+        x = synth.tile_inputs(spec)
+        if j["op"] == "recon":
+            assert np.array_equal(j["out"].cpu().numpy(), oracle.mr_fh(x[0], x[1], 8))
+        else:
+            s, n = oracle.edt_rounds(x, 8)
+            assert np.array_equal(j["sqdist"].cpu().numpy(), s) and np.array_equal(j["nearest"].cpu().numpy(), n)
+    g = ctx.batch_graph(jobs)
+    g.launch()
+    torch.cuda.synchronize()
+    assert g.stats()["status"] == 0
+    g.close()
+    ctx.close()
