@@ -439,16 +439,33 @@ __device__ void store_cols(const MrArgs& a, uint32_t t, const WaveLds& L, bool m
   }
 }
 
+// Rows and columns of the tile that changed since each axis scan last ran
+// (bit = row or column index, wave-uniform).  After a scan in direction D
+// every pixel dominates the offers of its D-predecessors (the pixel before it
+// along D: left for rows forward, right for rows backward, the row above --
+// three pixels with 8-connectivity -- for columns forward, the row below for
+// columns backward), and it keeps dominating them until one of those
+// predecessors rises.  So a scan only needs the 16-wide chunks whose
+// predecessors changed since it last ran, plus any chunk after one that it
+// has just changed; and the tile is locally stable exactly when all four sets
+// are empty (the four scans' predecessors are all eight neighbours, or all
+// four).  Changes made by a row scan are known per row (lane = row) and per
+// chunk of columns; those of a column scan per column and per chunk of rows.
+struct Dirty {
+  uint64_t r_cf, r_cb;  // rows changed since the last column scan forward / backward
+  uint64_t c_rf, c_rb;  // columns changed since the last row scan forward / backward
+  __device__ bool empty() const { return (r_cf | r_cb | c_rf | c_rb) == 0ull; }
+};
+
 // Apply every halo pixel's offer to the border pixels it touches, once:
 // J(p) <- max(J(p), min(J(h), I(p))) for border pixel p and halo neighbour h.
 // Halo pixels do not change during a visit and J only rises, so afterwards no
 // halo offer can raise anything again and the scans can ignore the halo (it
 // acts as zeros there).  Rows first, then columns, so a corner pixel takes
-// both.  Returns (wave-uniform) whether a pixel rose.
+// both.  Sets the rows and the columns that hold a border pixel that rose.
 template <int CONN>
-__device__ bool fold_halo(WaveLds& L) {
+__device__ void fold_halo(WaveLds& L, uint64_t& rows, uint64_t& cols) {
   const int l = lane();
-  bool up = false;
   auto offer = [&](int hy0, int hx0, int hy1, int hx1, int hy2, int hx2) {  // max of the halo neighbours
     uint32_t h = L.J[lidx(hy1, hx1)];
     if (CONN == 8) h = umax(h, umax((uint32_t)L.J[lidx(hy0, hx0)], (uint32_t)L.J[lidx(hy2, hx2)]));
@@ -459,7 +476,7 @@ __device__ bool fold_halo(WaveLds& L) {
   const uint32_t nt = umax(jt, umin(ht, it)), nb = umax(jb, umin(hb, ib));
   L.J[lidx(0, l)] = (uint8_t)nt;
   L.J[lidx(T - 1, l)] = (uint8_t)nb;
-  up |= nt != jt || nb != jb;
+  const uint64_t top = ballot(nt != jt), bot = ballot(nb != jb);  // lane = column
   // The column phase reads corners that other lanes wrote in the row phase
   // (lane 63 wrote (0, 63), lane 0 wrote (63, 0)): order the two phases.
   wave_sync();
@@ -468,9 +485,10 @@ __device__ bool fold_halo(WaveLds& L) {
   const uint32_t nl = umax(jl, umin(hl, il)), nr = umax(jr, umin(hr, ir));
   L.J[lidx(l, 0)] = (uint8_t)nl;
   L.J[lidx(l, T - 1)] = (uint8_t)nr;
-  up |= nl != jl || nr != jr;
+  const uint64_t left = ballot(nl != jl), right = ballot(nr != jr);  // lane = row
   wave_sync();
-  return ballot(up) != 0u;
+  rows = left | right | (top ? 1ull : 0ull) | (bot ? 1ull << (T - 1) : 0ull);
+  cols = top | bot | (left ? 1ull : 0ull) | (right ? 1ull << (T - 1) : 0ull);
 }
 
 // One axis scan of the tile in LDS, after `fold_halo`: the halo is ignored.
@@ -479,8 +497,18 @@ __device__ bool fold_halo(WaveLds& L) {
 // horizontal scans walk the columns with lane = row, using the previous
 // column.  Steps are loaded from LDS in chunks of kChunk so the wave pays one
 // LDS latency per chunk rather than per step; a chunk's results are written
-// back if any of them changed, and increases accumulate in `ch`.
+// back if any of them changed, and increases accumulate in `ch`.  A chunk
+// whose predecessors did not change since this scan last ran (`Dirty`), and
+// that follows no chunk this scan changed, is skipped; the chunk after a
+// skipped one reads its carried-in neighbour values from LDS.
 constexpr int kChunk = 16;
+static_assert(T == 4 * kChunk, "four chunks per scan");
+
+// Predecessor lines of chunk [x0, x0 + 16) in the scan's direction.
+__device__ __forceinline__ uint64_t chunk_preds(int x0, bool forward) {
+  const uint64_t w = 0xFFFFull << x0;
+  return forward ? w >> 1 : w << 1;
+}
 
 // Row scans (lane = row) on packed words: one step is a byte-selecting max of
 // the old pixel and the previous result, then a byte-selecting min with the
@@ -500,16 +528,25 @@ constexpr int kChunk = 16;
         : "v"(m_), "v"(I));                                                                             \
   } while (0)
 
-template <bool kForward>
-__device__ __forceinline__ void row_scan(WaveLds& L, uint32_t& ch) {
+template <bool kForward, bool kDirty>
+__device__ __forceinline__ void row_scan(WaveLds& L, uint32_t& ch, Dirty& dm) {
   const int l = lane();
+  uint64_t& mine = kForward ? dm.c_rf : dm.c_rb;
+  uint64_t& other = kForward ? dm.c_rb : dm.c_rf;
   uint32_t pw = 0;  // word holding the previous result: byte 3 (forward) or byte 0 (backward)
+  bool carried = true;  // pw holds the previous chunk's result (the halo's zero before the first)
+  bool carry = false;   // the previous chunk changed
   uint32_t acc = 0;
 #pragma unroll 1
   for (int c = 0; c < T / kChunk; ++c) {
     const int x0 = (kForward ? c : T / kChunk - 1 - c) * kChunk;
+    if (kDirty && !carry && (mine & chunk_preds(x0, kForward)) == 0ull) {
+      carried = false;
+      continue;
+    }
     uint32_t* jp = reinterpret_cast<uint32_t*>(&L.J[lidx(l, x0)]);
     const uint32_t* ip = reinterpret_cast<const uint32_t*>(&L.I[lidx(l, x0)]);
+    if (!carried) pw = kForward ? jp[-1] : jp[4];
     uint32_t w0 = jp[0], w1 = jp[1], w2 = jp[2], w3 = jp[3];
     const uint32_t o0 = w0, o1 = w1, o2 = w2, o3 = w3;
     const uint32_t i0 = ip[0], i1 = ip[1], i2 = ip[2], i3 = ip[3];
@@ -526,46 +563,64 @@ __device__ __forceinline__ void row_scan(WaveLds& L, uint32_t& ch) {
       MR_HSTEP(w0, w1, i0, 3, 0); MR_HSTEP(w0, w0, i0, 2, 3); MR_HSTEP(w0, w0, i0, 1, 2); MR_HSTEP(w0, w0, i0, 0, 1);
       pw = w0;
     }
+    carried = true;
     const uint32_t d = (o0 ^ w0) | (o1 ^ w1) | (o2 ^ w2) | (o3 ^ w3);
-    if (ballot(d != 0u) != 0u) {  // a chunk that changed nothing is not written back
+    const uint64_t rows = ballot(d != 0u);
+    carry = rows != 0ull;
+    if (carry) {  // a chunk that changed nothing is not written back
       jp[0] = w0;
       jp[1] = w1;
       jp[2] = w2;
       jp[3] = w3;
+      if (kDirty) {
+        dm.r_cf |= rows;
+        dm.r_cb |= rows;
+        other |= 0xFFFFull << x0;
+      }
     }
     acc |= d;
   }
+  mine = 0ull;
   ch |= acc;
   wave_sync();
 }
 #undef MR_HSTEP
 
-template <int CONN, bool kVertical, bool kForward>
-__device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
+template <int CONN, bool kVertical, bool kForward, bool kDirty>
+__device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch, Dirty& dm) {
   const int l = lane();
   if (!kVertical) {
-    row_scan<kForward>(L, ch);
+    row_scan<kForward, kDirty>(L, ch, dm);
     return;
   }
+  uint64_t& mine = kForward ? dm.r_cf : dm.r_cb;
+  uint64_t& other = kForward ? dm.r_cb : dm.r_cf;
   uint32_t prev = 0;
+  bool carried = true;  // prev holds the previous chunk's last row (the halo's zero before the first)
+  bool carry = false;   // the previous chunk changed
   // Vertical 8-connected scans take the diagonal offers of the previous row
   // from the adjacent lanes, with the max folded into a zero-filled lane
   // shift (lanes 0 and 63 have no in-tile neighbour on one side).
 #pragma unroll 1
   for (int c = 0; c < T / kChunk; ++c) {
+    const int y0 = (kForward ? c : T / kChunk - 1 - c) * kChunk;
+    if (kDirty && !carry && (mine & chunk_preds(y0, kForward)) == 0ull) {
+      carried = false;
+      continue;
+    }
+    if (!carried) prev = L.J[lidx(kForward ? y0 - 1 : y0 + kChunk, l)];
     uint32_t vj[kChunk], vi[kChunk];
     const uint32_t ch0 = ch;
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
-      const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
-      const int at = kVertical ? lidx(s, l) : lidx(l, s);
-      vj[k] = L.J[at];
-      vi[k] = L.I[at];
+      const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
+      vj[k] = L.J[lidx(s, l)];
+      vi[k] = L.I[lidx(s, l)];
     }
 #pragma unroll
     for (int k = 0; k < kChunk; ++k) {
       uint32_t nv;
-      if (kVertical && CONN == 8) {
+      if (CONN == 8) {
         // J <= I throughout, so min(max(J, offers), I) needs no median.  The
         // two lane shifts are fused into the max (DPP with zero fill; the
         // s_nop gives the two wait states a DPP read of a just-written
@@ -588,63 +643,25 @@ __device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch) {
       vj[k] = nv;
       prev = nv;
     }
-    if (ballot(ch != ch0) != 0u) {  // a chunk that changed nothing is not written back
+    carried = true;
+    const uint64_t cols = ballot(ch != ch0);
+    carry = cols != 0ull;
+    if (carry) {  // a chunk that changed nothing is not written back
 #pragma unroll
       for (int k = 0; k < kChunk; ++k) {
-        const int s = kForward ? c * kChunk + k : T - 1 - (c * kChunk + k);
-        L.J[kVertical ? lidx(s, l) : lidx(l, s)] = (uint8_t)vj[k];
+        const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
+        L.J[lidx(s, l)] = (uint8_t)vj[k];
+      }
+      if (kDirty) {
+        dm.c_rf |= cols;
+        dm.c_rb |= cols;
+        other |= 0xFFFFull << y0;
       }
     }
     asm volatile("" ::: "memory");  // keep chunks apart: bounded register use
   }
+  mine = 0ull;
   wave_sync();
-}
-
-// Is the tile in LDS locally stable, i.e. no tile pixel q with J(q) < I(q)
-// has a neighbour p (tile or halo) with J(p) > J(q)?  That is the condition
-// four quiet scans establish, tested in one top-to-bottom walk with lane =
-// column.  h(y) is the largest horizontal neighbour of row y (the halo
-// columns enter through column 65's zeros, as in the scans) and s(y) =
-// max(h(y), J(y)); q in row y sees max(h(y), J(y-1), J(y+1)) with
-// 4-connectivity and max(h(y), s(y-1), s(y+1)) with 8-connectivity.
-template <int CONN>
-__device__ bool lds_settled(const WaveLds& L) {
-  const int l = lane();
-  const int hc = l == 0 ? -1 : (l == T - 1 ? T : kZeroCol);
-  auto hnb = [&](uint32_t j, int y) {
-    return umax(umax(from_left0(j), from_right0(j)), (uint32_t)L.J[lidx(y, hc)]);
-  };
-  uint32_t jp = L.J[lidx(-1, l)];
-  uint32_t sp = CONN == 8 ? umax(hnb(jp, -1), jp) : jp;  // s(y-1) (J(y-1) for 4-conn)
-  uint32_t jc = L.J[lidx(0, l)], ic = L.I[lidx(0, l)];
-  uint32_t hcur = hnb(jc, 0);
-#pragma unroll 1
-  for (int c = 0; c < T / kChunk; ++c) {
-    uint32_t nj[kChunk], ni[kChunk], nf[kChunk];
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-      const int y = c * kChunk + k + 1;  // row below the one tested
-      nj[k] = L.J[lidx(y, l)];
-      ni[k] = y < T ? L.I[lidx(y, l)] : 0u;
-      nf[k] = L.J[lidx(y, hc)];
-    }
-    bool raisable = false;
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-      const uint32_t jn = nj[k];
-      const uint32_t hn = umax(umax(from_left0(jn), from_right0(jn)), nf[k]);
-      const uint32_t sn = CONN == 8 ? umax(hn, jn) : jn;
-      const uint32_t m = umax(umax(sp, sn), hcur);
-      raisable |= jc < umin(m, ic);
-      sp = CONN == 8 ? umax(hcur, jc) : jc;
-      jc = jn;
-      ic = ni[k];
-      hcur = hn;
-    }
-    if (ballot(raisable) != 0u) return false;
-    asm volatile("" ::: "memory");
-  }
-  return true;
 }
 
 // Sweep the tile in LDS until it is locally stable, or `max_it` iterations.
@@ -653,39 +670,55 @@ __device__ bool lds_settled(const WaveLds& L) {
 // (N^{-,0}), column-wise backward (N^{0,-}).  Every step is one elementary
 // update J(p) <- max(J(p), J(q in the scan's neighbour set)) ^ I(p), so the
 // tile never leaves [J ^ I, rho_I(J)].  Halo pixels are sources only, and
-// `fold_halo` applies all their offers before the first scan.  Four
-// consecutive scans that change nothing (one of each direction, in any
-// phase) mean every pixel already dominates each of its neighbours' offers:
-// the tile is stable.  The same holds when the one-pass test `lds_settled`
-// finds no raisable pixel.  With 8-connectivity the test runs after every
-// scan that changed nothing, which usually ends the sweep one scan after the
-// last change instead of four; with 4-connectivity a scan costs about half
-// as much as the test, which then does not pay.  Returns true if the tile is
-// locally stable; `changed` tells whether any scan changed a pixel.
+// `fold_halo` applies all their offers before the first scan.
+//
+// When the sweep stops.  With 8-connectivity the scans track what changed
+// (`Dirty`): a scan with nothing to do costs nothing, and the tile is stable
+// when no scan has anything left.  `all_dirty`: the tile as loaded is not
+// known to be locally stable (a seed-pass tile, a tile the sweep cap stopped,
+// a full round); otherwise its last visit left it stable and only the border
+// pixels the halo raised start dirty.  With 4-connectivity changes spread
+// over most of a tile and the bookkeeping measured slower (1.86 against
+// 1.84 ms on the 16384^2 workload, against 1.54 and 1.65 ms with
+// 8-connectivity): there four consecutive scans that change nothing (one of
+// each direction, in any phase) mean every pixel dominates each of its
+// neighbours' offers.  Returns true if the tile is locally stable;
+// `changed` tells whether any pixel rose.
 template <int CONN>
-__device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed, int start = 0) {
-  int quiet = 0;  // consecutive scans that changed nothing
-  changed = fold_halo<CONN>(L);
+__device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& changed, bool all_dirty, int start = 0) {
+  constexpr bool kDirty = CONN == 8;
+  uint64_t rows, cols;
+  fold_halo<CONN>(L, rows, cols);
+  changed = (rows | cols) != 0ull;
+  Dirty dm;
+  if (all_dirty || !kDirty) {
+    dm.r_cf = dm.r_cb = dm.c_rf = dm.c_rb = ~0ull;
+  } else {
+    dm.r_cf = dm.r_cb = rows;
+    dm.c_rf = dm.c_rb = cols;
+  }
+  int quiet = 0;  // consecutive scans that changed nothing (4-connectivity)
   // `start` picks the first scan (0 rows forward, 1 columns forward, 2 rows
   // backward, 3 columns backward), e.g. the one that carries a raised halo
   // side into the tile; the cyclic order is Algorithm 5's.
   for (int n = 0; n < 4 * max_it; ++n) {
+    if (kDirty && dm.empty()) return true;
     if ((n & 3) == 0) iters++;
     uint32_t ch = 0;
     switch ((start + n) & 3) {
-      case 0: scan<CONN, false, true>(L, ch); break;
-      case 1: scan<CONN, true, true>(L, ch); break;
-      case 2: scan<CONN, false, false>(L, ch); break;
-      default: scan<CONN, true, false>(L, ch); break;
+      case 0: if (!kDirty || dm.c_rf) scan<CONN, false, true, kDirty>(L, ch, dm); break;
+      case 1: if (!kDirty || dm.r_cf) scan<CONN, true, true, kDirty>(L, ch, dm); break;
+      case 2: if (!kDirty || dm.c_rb) scan<CONN, false, false, kDirty>(L, ch, dm); break;
+      default: if (!kDirty || dm.r_cb) scan<CONN, true, false, kDirty>(L, ch, dm); break;
     }
     if (ballot(ch != 0u) != 0u) {
-      quiet = 0;
       changed = true;
-    } else if (++quiet == 4 || (CONN == 8 && lds_settled<CONN>(L))) {
+      quiet = 0;
+    } else if (!kDirty && ++quiet == 4) {
       return true;
     }
   }
-  return false;
+  return kDirty && dm.empty();
 }
 
 // Can the (possibly stale) halo pixel (qy, qx) be raised by interior value v?
@@ -873,7 +906,7 @@ __device__ void seed_visit(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
   uint32_t it = 0;
   bool changed;
-  const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it, changed);
+  const bool stable = sweep_tile<CONN>(L, a.seed_sweeps, it, changed, true);
   iters += it;
   store_tile(tr, L);
   store_cols(a, t, L, true);
@@ -894,6 +927,7 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
                            uint32_t& visits, uint32_t& iters, uint32_t& seeds) {
   const TileRef tr = tile_ref(a, t);
   int start = 0;
+  bool all_dirty = true;
   if (check) {
     load_region<false>(tr, L, false, a.cols, a.ntiles * 256u, t);
     if (!lds_dirty<CONN>(L, seeds)) return;
@@ -914,6 +948,7 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
       sides = border_raisable<CONN>(L);
       if (readlane(uns, 0) == 0u && sides == 0u) return;
     }
+    all_dirty = readlane(uns, 0) != 0u;
     // First scan: the one moving away from a raisable side (top: columns
     // forward, bottom: columns backward, left: rows forward, right: rows backward).
     start = (sides & 1u) ? 1 : (sides & 2u) ? 3 : (sides & 4u) ? 0 : (sides & 8u) ? 2 : 0;
@@ -923,7 +958,7 @@ __device__ void visit_tile(const MrArgs& a, WaveLds& L, WaveStage& s, const Next
   const uint32_t ol = L.J[lidx(l, 0)], orr = L.J[lidx(l, T - 1)];
   uint32_t it = 0;
   bool changed;
-  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it, changed, start);
+  const bool stable = sweep_tile<CONN>(L, a.max_sweeps, it, changed, all_dirty, start);
   iters += it;
   visits++;
   if (lane() == 0) cstore(a.unsettled + t, stable ? 0u : 1u);
