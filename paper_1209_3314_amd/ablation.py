@@ -104,7 +104,7 @@ def run(side: int = 4096, reps: int = 5, sweeps=(1, 2, 4, 8), conn: int = 4) -> 
         base_t = _time(torch, lambda: ctx.morph_recon(Jd, Id, conn, out=out), reps)
         over.append({"design": "tile", "capacity": 0, "restarts": 0, "ms": round(base_t, 4), "ratio": 1.0})
         found = set()
-        for f in (0.9, 0.7, 0.5, 0.3, 0.2, 0.1, 0.05):
+        for f in (0.999, 0.99, 0.97, 0.95, 0.9, 0.7, 0.5, 0.3, 0.2, 0.1, 0.05):
             cap = max(1, int(tiles * f))
             ctx.set_options(mr_list_capacity=cap)
             ms = _time(torch, lambda: ctx.morph_recon(Jd, Id, conn, out=out), reps)

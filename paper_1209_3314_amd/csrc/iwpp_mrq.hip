@@ -68,7 +68,15 @@ struct Appender {
   __device__ void push(bool pred, uint32_t item) {
     if (a.mode == IWPP_QUEUE_NAIVE) {
       if (pred) {
-        const uint32_t slot = atomic_add(cnt, 1u);
+        // One device-scope atomic per item.  Written out because the
+        // compiler would otherwise combine the wave's increments of one
+        // address into a single atomic (mbcnt offsets), which is the ballot
+        // mode; the wait is inside the same statement.
+        uint32_t slot;
+        asm volatile("global_atomic_add %0, %1, %2, off sc0\n\ts_waitcnt vmcnt(0)"
+                     : "=&v"(slot)
+                     : "v"(cnt), "v"(1u)
+                     : "memory");
         if (slot < a.cap) cstore(list + slot, item);
         else cstore(lost, 1u);
       }
