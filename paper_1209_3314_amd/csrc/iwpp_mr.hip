@@ -586,81 +586,117 @@ __device__ __forceinline__ void row_scan(WaveLds& L, uint32_t& ch, Dirty& dm) {
 }
 #undef MR_HSTEP
 
-template <int CONN, bool kVertical, bool kForward, bool kDirty>
-__device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch, Dirty& dm) {
+// min(v, byte B of w) for a byte-sized v (SDWA selects the mask byte).
+template <int B>
+__device__ __forceinline__ uint32_t min_byte(uint32_t v, uint32_t w) {
+  uint32_t r;
+  if (B == 0)
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(v), "v"(w));
+  else if (B == 1)
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(v), "v"(w));
+  else if (B == 2)
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(v), "v"(w));
+  else
+    asm("v_min_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(v), "v"(w));
+  return r;
+}
+
+// The tile's mask column of this lane, four rows per word (row 4w + b in byte
+// b of ic[w]): the mask does not change during a visit, so the column scans
+// take it from registers and read only J from LDS.
+__device__ __forceinline__ void load_mask_column(const WaveLds& L, uint32_t (&ic)[T / 4]) {
   const int l = lane();
+#pragma unroll
+  for (int w = 0; w < T / 4; ++w) {
+    const uint32_t b0 = L.I[lidx(4 * w, l)], b1 = L.I[lidx(4 * w + 1, l)], b2 = L.I[lidx(4 * w + 2, l)],
+                   b3 = L.I[lidx(4 * w + 3, l)];
+    ic[w] = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+  }
+}
+
+template <int CONN, bool kForward, bool kDirty, int C>
+__device__ __forceinline__ void column_chunk(WaveLds& L, uint32_t& ch, Dirty& dm, const uint32_t (&ic)[T / 4],
+                                             uint32_t& prev, bool& carried, bool& carry) {
+  const int l = lane();
+  constexpr int y0 = (kForward ? C : T / kChunk - 1 - C) * kChunk;
+  uint64_t& mine = kForward ? dm.r_cf : dm.r_cb;
+  uint64_t& other = kForward ? dm.r_cb : dm.r_cf;
+  if (kDirty && !carry && (mine & chunk_preds(y0, kForward)) == 0ull) {
+    carried = false;
+    return;
+  }
+  if (!carried) prev = L.J[lidx(kForward ? y0 - 1 : y0 + kChunk, l)];
+  uint32_t vj[kChunk];
+  const uint32_t ch0 = ch;
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
+    vj[k] = L.J[lidx(s, l)];
+  }
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
+    const uint32_t iw = ic[s / 4];
+    uint32_t m;
+    if (CONN == 8) {
+      // The two lane shifts of the diagonal offers are fused into the max
+      // (DPP with zero fill; the s_nop gives the two wait states a DPP read
+      // of a just-written register needs).
+      uint32_t ml, mr;
+      asm("s_nop 1\n\t"
+          "v_max_u32_dpp %0, %2, %3 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_max_u32_dpp %1, %2, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+          : "=&v"(ml), "=&v"(mr)
+          : "v"(prev), "v"(vj[k]));
+      m = umax(ml, mr);
+    } else {
+      m = umax(vj[k], prev);
+    }
+    // J <= I throughout, so min(max(J, offers), I) is the update.
+    uint32_t nv;
+    switch (s & 3) {
+      case 0: nv = min_byte<0>(m, iw); break;
+      case 1: nv = min_byte<1>(m, iw); break;
+      case 2: nv = min_byte<2>(m, iw); break;
+      default: nv = min_byte<3>(m, iw); break;
+    }
+    // Values only rise, so the sum of increases is nonzero iff something changed.
+    ch += nv - vj[k];
+    vj[k] = nv;
+    prev = nv;
+  }
+  carried = true;
+  const uint64_t cols = ballot(ch != ch0);
+  carry = cols != 0ull;
+  if (carry) {  // a chunk that changed nothing is not written back
+#pragma unroll
+    for (int k = 0; k < kChunk; ++k) {
+      const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
+      L.J[lidx(s, l)] = (uint8_t)vj[k];
+    }
+    if (kDirty) {
+      dm.c_rf |= cols;
+      dm.c_rb |= cols;
+      other |= 0xFFFFull << y0;
+    }
+  }
+  asm volatile("" ::: "memory");  // keep chunks apart: bounded register use
+}
+
+template <int CONN, bool kVertical, bool kForward, bool kDirty>
+__device__ __forceinline__ void scan(WaveLds& L, uint32_t& ch, Dirty& dm, const uint32_t (&ic)[T / 4]) {
   if (!kVertical) {
     row_scan<kForward, kDirty>(L, ch, dm);
     return;
   }
-  uint64_t& mine = kForward ? dm.r_cf : dm.r_cb;
-  uint64_t& other = kForward ? dm.r_cb : dm.r_cf;
   uint32_t prev = 0;
   bool carried = true;  // prev holds the previous chunk's last row (the halo's zero before the first)
   bool carry = false;   // the previous chunk changed
-  // Vertical 8-connected scans take the diagonal offers of the previous row
-  // from the adjacent lanes, with the max folded into a zero-filled lane
-  // shift (lanes 0 and 63 have no in-tile neighbour on one side).
-#pragma unroll 1
-  for (int c = 0; c < T / kChunk; ++c) {
-    const int y0 = (kForward ? c : T / kChunk - 1 - c) * kChunk;
-    if (kDirty && !carry && (mine & chunk_preds(y0, kForward)) == 0ull) {
-      carried = false;
-      continue;
-    }
-    if (!carried) prev = L.J[lidx(kForward ? y0 - 1 : y0 + kChunk, l)];
-    uint32_t vj[kChunk], vi[kChunk];
-    const uint32_t ch0 = ch;
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-      const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
-      vj[k] = L.J[lidx(s, l)];
-      vi[k] = L.I[lidx(s, l)];
-    }
-#pragma unroll
-    for (int k = 0; k < kChunk; ++k) {
-      uint32_t nv;
-      if (CONN == 8) {
-        // J <= I throughout, so min(max(J, offers), I) needs no median.  The
-        // two lane shifts are fused into the max (DPP with zero fill; the
-        // s_nop gives the two wait states a DPP read of a just-written
-        // register needs).
-        uint32_t ml, mr;
-        asm("s_nop 1\n\t"
-            "v_max_u32_dpp %0, %2, %3 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-            "v_max_u32_dpp %1, %2, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-            : "=&v"(ml), "=&v"(mr)
-            : "v"(prev), "v"(vj[k]));
-        nv = umin(umax(ml, mr), vi[k]);
-      } else {
-        // min(max(J, prev), I) is the median of the three because J <= I
-        asm("v_med3_u32 %0, %1, %2, %3" : "=v"(nv) : "v"(vj[k]), "v"(prev), "v"(vi[k]));
-      }
-      // Values only rise (J <= I holds throughout), so the sum of increases
-      // is nonzero iff something changed; a sum keeps the compiler from
-      // deferring per-step comparisons and holding old values live.
-      ch += nv - vj[k];
-      vj[k] = nv;
-      prev = nv;
-    }
-    carried = true;
-    const uint64_t cols = ballot(ch != ch0);
-    carry = cols != 0ull;
-    if (carry) {  // a chunk that changed nothing is not written back
-#pragma unroll
-      for (int k = 0; k < kChunk; ++k) {
-        const int s = kForward ? y0 + k : y0 + kChunk - 1 - k;
-        L.J[lidx(s, l)] = (uint8_t)vj[k];
-      }
-      if (kDirty) {
-        dm.c_rf |= cols;
-        dm.c_rb |= cols;
-        other |= 0xFFFFull << y0;
-      }
-    }
-    asm volatile("" ::: "memory");  // keep chunks apart: bounded register use
-  }
-  mine = 0ull;
+  column_chunk<CONN, kForward, kDirty, 0>(L, ch, dm, ic, prev, carried, carry);
+  column_chunk<CONN, kForward, kDirty, 1>(L, ch, dm, ic, prev, carried, carry);
+  column_chunk<CONN, kForward, kDirty, 2>(L, ch, dm, ic, prev, carried, carry);
+  column_chunk<CONN, kForward, kDirty, 3>(L, ch, dm, ic, prev, carried, carry);
+  (kForward ? dm.r_cf : dm.r_cb) = 0ull;
   wave_sync();
 }
 
@@ -698,6 +734,8 @@ __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& change
     dm.r_cf = dm.r_cb = rows;
     dm.c_rf = dm.c_rb = cols;
   }
+  uint32_t ic[T / 4];
+  load_mask_column(L, ic);
   int quiet = 0;        // consecutive scans that changed nothing (4-connectivity)
   bool scanned = false;  // some scan of this visit changed a pixel
   // `start` picks the first scan (0 rows forward, 1 columns forward, 2 rows
@@ -708,10 +746,10 @@ __device__ bool sweep_tile(WaveLds& L, int max_it, uint32_t& iters, bool& change
     if ((n & 3) == 0) iters++;
     uint32_t ch = 0;
     switch ((start + n) & 3) {
-      case 0: if (!kDirty || dm.c_rf) scan<CONN, false, true, kDirty>(L, ch, dm); break;
-      case 1: if (!kDirty || dm.r_cf) scan<CONN, true, true, kDirty>(L, ch, dm); break;
-      case 2: if (!kDirty || dm.c_rb) scan<CONN, false, false, kDirty>(L, ch, dm); break;
-      default: if (!kDirty || dm.r_cb) scan<CONN, true, false, kDirty>(L, ch, dm); break;
+      case 0: if (!kDirty || dm.c_rf) scan<CONN, false, true, kDirty>(L, ch, dm, ic); break;
+      case 1: if (!kDirty || dm.r_cf) scan<CONN, true, true, kDirty>(L, ch, dm, ic); break;
+      case 2: if (!kDirty || dm.c_rb) scan<CONN, false, false, kDirty>(L, ch, dm, ic); break;
+      default: if (!kDirty || dm.r_cb) scan<CONN, true, false, kDirty>(L, ch, dm, ic); break;
     }
     if (ballot(ch != 0u) != 0u) {
       changed = true;
