@@ -183,11 +183,20 @@ def serve_leg(ctx, iw, torch, np, gen, rates, seconds: float, burst: int) -> dic
                        "70% reconstruction / 30% EDT, conn 8; Poisson arrivals; host buffers pinned; 64 GiB budget; "
                        "every request uploads its inputs to fresh device memory, so pool reuse gives no cache reuse",
            "pool_mpix": round(sum(npx) / 1e6, 1), "rates": []}
+    # Each rate runs batched, plain, plain, batched (seconds / 2 each, two
+    # arrival traces), so neither mode always runs first; a mode's figures pool
+    # its two runs.
     for rate in rates:
-        arr = synth.serve_arrivals(rate, seconds, SERVE_POOL)
-        row = {"rate_req_s": rate, "seconds": seconds, "requests": len(arr)}
-        for mode, mb in (("batched", 0), ("plain", 1)):
-            row[mode] = summary(arr, *run(mb, arr))
+        arrs = [synth.serve_arrivals(rate, seconds / 2, SERVE_POOL, seed=k) for k in (0, 1)]
+        row = {"rate_req_s": rate, "seconds": seconds, "requests": sum(len(a) for a in arrs), "order": "ABBA"}
+        got = {"batched": [], "plain": []}
+        for mode, k in (("batched", 0), ("plain", 0), ("plain", 1), ("batched", 1)):
+            got[mode].append((arrs[k], run(0 if mode == "batched" else 1, arrs[k])))
+        for mode in ("batched", "plain"):
+            (a0, (l0, s0, st0, e0)), (a1, (l1, s1, st1, e1)) = got[mode]
+            st = {"batches": st0["batches"] + st1["batches"], "max_batch_jobs": max(st0["max_batch_jobs"], st1["max_batch_jobs"]),
+                  "peak_bytes": max(st0["peak_bytes"], st1["peak_bytes"]), "failed": st0["failed"] + st1["failed"]}
+            row[mode] = summary(a0 + a1, np.concatenate([l0, l1]), s0 + s1, st, e0 and e1)
             log(f"serve rate {rate} {mode}: {row[mode]}")
         row["p99_plain_over_batched"] = round(row["plain"]["p99_ms"] / max(row["batched"]["p99_ms"], 1e-9), 3)
         res["rates"].append(row)

@@ -12,7 +12,11 @@
 // takes the admitted jobs whose uploads have finished; at most two batches are
 // queued on the compute stream, so the device goes from one batch to the next
 // without a host round trip while later arrivals still join the batch after,
-// and uploads, computation and downloads of successive batches overlap.
+// and uploads, computation and downloads of successive batches overlap.  While
+// a batch computes and uploads are still arriving, the next batch waits until
+// it is at least as large as the computing one (bursts form large batches),
+// and an idle device takes the oldest job alone (it completes as a plain call
+// would; the others follow in the next batch).
 // Batches share the context's fixed area and one scratch buffer: they run one
 // after another in stream order.  A batch runs as one launch sequence per
 // (operation, connectivity) group; each group's jobs are downloaded and
@@ -122,6 +126,7 @@ struct Part {
 
 struct Batch {
   std::vector<Part> parts;
+  size_t jobs = 0;
   size_t next = 0;  // first part not yet complete
   int slot = -1;
   bool failed = false;  // the launch sequence could not be enqueued
@@ -343,10 +348,13 @@ struct iwpp_server {
   bool launch() {
     if (admitted.empty() || broken) return false;
     int computing = 0;  // batches whose last group has not finished computing
+    size_t computing_jobs = 0;
     for (const Batch& q : inflight)
       if (!q.failed && !q.parts.empty() && q.parts.back().done &&
-          hipEventQuery(q.parts.back().done) == hipErrorNotReady)
+          hipEventQuery(q.parts.back().done) == hipErrorNotReady) {
         computing++;
+        computing_jobs = q.jobs > computing_jobs ? q.jobs : computing_jobs;
+      }
     if (computing >= kMaxComputingBatches) return false;
     int slot = -1;
     for (int s = 0; s < kSlots; ++s)
@@ -360,12 +368,16 @@ struct iwpp_server {
     // downloads proceed on the copy streams.
     std::vector<iwpp_job> dj;
     std::vector<uint64_t> tk;
+    bool uploading = false;  // a later admitted job's upload has not finished
     {
       std::lock_guard<std::mutex> g(mu);
       for (uint64_t t : admitted) {
         if ((int)dj.size() >= opt.max_batch) break;
         const hipError_t q = jobs[t].up ? hipEventQuery(jobs[t].up) : hipSuccess;
-        if (q == hipErrorNotReady) break;
+        if (q == hipErrorNotReady) {
+          uploading = true;
+          break;
+        }
         if (q != hipSuccess) {
           (void)hipGetLastError();
           broken = true;
@@ -377,6 +389,19 @@ struct iwpp_server {
       }
     }
     if (dj.empty()) return false;
+    // While a batch computes and uploads are still arriving (a burst), wait
+    // until the next batch is at least as large as the computing one: every
+    // launch sequence has a fixed cost, and small batches launched one after
+    // another would pay it per handful of jobs.  An idle device launches at
+    // once, so light load keeps its latency.
+    if (computing > 0 && uploading && dj.size() < computing_jobs && (int)dj.size() < opt.max_batch) return false;
+    // An idle device takes the oldest job alone, so that it completes as a
+    // plain call would; the jobs ready with it form the next batch, queued
+    // right behind it.
+    if (computing == 0 && dj.size() > 1) {
+      dj.resize(1);
+      tk.resize(1);
+    }
     iwpp::rt::Plan plan;
     size_t n = dj.size();
     for (;;) {  // shrink the batch until its scratch and tables fit
@@ -397,6 +422,7 @@ struct iwpp_server {
     tk.resize(n);
     Batch b;
     b.slot = slot;
+    b.jobs = n;
     // One part per plan group, holding that group's tickets in plan order
     // (build_plan keeps the jobs' order inside a group).
     for (const iwpp::rt::Group& g : plan.groups) {
