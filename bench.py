@@ -35,6 +35,10 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpixel/s morph-recon & EDT (bit-exact) + batched p50/p99 tile latency vs plain"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+# Launch options per operation chosen by the library's autotuner on its own
+# synthetic inputs of each size bucket (python -m paper_1209_3314_amd.tune);
+# results never depend on them.
+TUNED_FILE = os.path.join(ROOT, "paper_1209_3314_amd", "tuned", "gfx950.json")
 # The paper's own end-to-end speedups (context only: other hardware, other
 # images, several devices).
 PAPER_CONTEXT = {
@@ -521,6 +525,8 @@ def main():
     ap.add_argument("--batch-tiles", type=int, default=256, help="tiles in the batched leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-slide", action="store_true", help="skip the whole-slide reconstruction leg")
+    ap.add_argument("--options", choices=("tuned", "default"), default="tuned",
+                    help="launch options of the step: the autotuner's per-operation choice or the library defaults")
     ap.add_argument("--serve-rates", default="200,800,2000", help="comma-separated request rates (per second)")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="trace length per rate")
     ap.add_argument("--cpu-reps", type=int, default=3, help="oracle runs of the CPU baseline (median reported)")
@@ -603,21 +609,36 @@ def main():
     nr = torch.empty(Be.shape, dtype=torch.int32, device=dev)
     ctx = iw.Context(0, profile=True)
     parts = [("mr16k_conn8", 8), ("mr16k_conn4", 4), ("edt4k_conn8", 8)]
+    # Options per part: the autotuner's choice for the part's size bucket, or
+    # the library defaults (--options default).
+    from paper_1209_3314_amd import tune
+
+    opts = {name: dict(tune.DEFAULTS) for name, _ in parts}
+    if args.options == "tuned":
+        cache = tune.TuneCache(TUNED_FILE, tune._device_name(0), ctx._lib.iwpp_version())
+        for name, conn in parts:
+            op, npx = ("recon", n_mr) if name.startswith("mr") else ("edt", n_edt)
+            opts[name].update(cache.get(tune.bucket(op, conn, npx)) or {})
+    used = {name: {k: v for k, v in o.items() if v != tune.DEFAULTS[k]} for name, o in opts.items()}
+    log(f"launch options per part ({args.options}): {used}")
+
+    def call(name, conn):
+        ctx.set_options(**opts[name])
+        if name.startswith("mr"):
+            ctx.morph_recon(Jd, Id, conn, out=o8 if conn == 8 else o4)
+        else:
+            ctx.edt(Bd, conn, out=(sq, nr))
 
     def step():
-        ctx.morph_recon(Jd, Id, 8, out=o8)
-        ctx.morph_recon(Jd, Id, 4, out=o4)
-        ctx.edt(Bd, 8, out=(sq, nr))
+        for name, conn in parts:
+            call(name, conn)
 
     for _ in range(max(args.warmup, 1)):
         step()
     torch.cuda.synchronize()
     gpu_stats = {}
     for name, conn in parts:  # counters of one call each (not timed)
-        if name.startswith("mr"):
-            ctx.morph_recon(Jd, Id, conn, out=o8 if conn == 8 else o4)
-        else:
-            ctx.edt(Bd, conn, out=(sq, nr))
+        call(name, conn)
         gpu_stats[name] = ctx.stats()
         assert gpu_stats[name]["status"] == 0, gpu_stats[name]
     ctx.profile_read()  # drop the warm-up records
@@ -716,6 +737,7 @@ def main():
                                  "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                  "mpix_s": round(n / (ms * 1e-3) / 1e6, 1)}
 
+    ctx.set_options(**tune.DEFAULTS)  # the other legs run with the defaults (the batch leg tunes its own)
     slide = None
     if not args.no_slide:
         slide = slide_leg(ctx, torch, np)
@@ -747,6 +769,9 @@ def main():
         "per_op": op_roofline, "kernels_ms": {k: round(v, 4) for k, v in kernels.items()},
         "wall_ms_per_step": round(wall_ms / args.steps, 4),
         "work": {"q_ref": q_ref, "gpu": gpu_stats},
+        "launch_options": {"mode": args.options, "per_part": used,
+                           "source": "autotuner cache paper_1209_3314_amd/tuned/gfx950.json" if args.options == "tuned"
+                           else "library defaults"},
         "edt_vs_exact": edt_vs_exact,
         "paper_context": PAPER_CONTEXT,
         "batch": batch,

@@ -297,3 +297,28 @@ class TunedContext(Context):
         # the options are read when the graph is captured
         self._apply("batch", 0, batch_pixels(jobs))
         return super().batch_graph(jobs)
+
+
+def main(argv=None) -> int:
+    """Tune buckets given as op:conn:pixels and write the cache, e.g.
+
+        python -m paper_1209_3314_amd.tune --out paper_1209_3314_amd/tuned/gfx950.json --reps 5 \\
+            recon:8:268435456 recon:4:268435456 edt:8:16777216
+    """
+    import argparse
+
+    ap = argparse.ArgumentParser(description=main.__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("buckets", nargs="+", help="op:conn:pixels (op = recon, edt or batch)")
+    ap.add_argument("--out", default=None, help="cache file (default: the per-user cache)")
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args(argv)
+    todo = []
+    for b in args.buckets:
+        op, conn, px = b.split(":")
+        todo.append((op, int(conn), int(px)))
+    autotune(todo, cache_path=args.out, reps=args.reps, force=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
