@@ -112,3 +112,34 @@ def test_tuned_batch_never_changes_results(tmp_path):
     assert g.stats()["status"] == 0
     g.close()
     ctx.close()
+
+
+def test_command_line_parses_buckets(monkeypatch, tmp_path):
+    """`python -m paper_1209_3314_amd.tune op:conn:pixels ...` tunes exactly the
+    named buckets into the given file (the tuning itself is stubbed: no GPU)."""
+    seen = {}
+
+    def fake_autotune(buckets, device=0, cache_path=None, reps=3, force=False):
+        seen.update(buckets=list(buckets), cache_path=cache_path, reps=reps, force=force)
+
+    monkeypatch.setattr(tune, "autotune", fake_autotune)
+    out = str(tmp_path / "c.json")
+    assert tune.main(["--out", out, "--reps", "5", "recon:8:268435456", "edt:8:16777216"]) == 0
+    assert seen == {"buckets": [("recon", 8, 268435456), ("edt", 8, 16777216)], "cache_path": out, "reps": 5,
+                    "force": True}
+
+
+def test_committed_cache_names_known_options():
+    """The cache the benchmark reads holds option sets the library accepts,
+    keyed by buckets of the benchmark's sizes."""
+    import os
+
+    path = os.path.join(os.path.dirname(tune.__file__), "tuned", "gfx950.json")
+    with open(path) as f:
+        d = json.load(f)
+    keys = {tune.bucket("recon", 8, 16384 * 16384), tune.bucket("recon", 4, 16384 * 16384),
+            tune.bucket("edt", 8, 4096 * 4096)}
+    assert keys <= set(d["entries"])
+    for e in d["entries"].values():
+        assert set(e["options"]) <= set(tune.DEFAULTS)
+        assert e["ms"] <= e["default_ms"]
