@@ -111,6 +111,25 @@ def test_tunings_do_not_change_bytes(env, opts):
     assert np.array_equal(g, oracle.mr_fh(J, I, 4))
 
 
+@pytest.mark.parametrize("conn,opts", [
+    (4, dict(wg_waves=8, stage_depth=16, mr_seed_strip=4, mr_seed_sweeps=2)),  # the benchmark's tuned options
+    (8, dict(stage_depth=16, mr_seed_strip=16)),
+    (8, dict(wg_waves=8, stage_depth=1, mr_seed_strip=1)),
+])
+def test_benchmark_options_do_not_change_bytes(env, conn, opts):
+    """Launch options of the benchmark step (and extreme stage/strip sizes)
+    over several hundred tiles with ragged edges."""
+    torch, iw, _ = env
+    J, I = synth.mr_inputs(1500, 1301, 21, n_disks=60, radius=(5, 30), offset=48)
+    ctx = iw.Context(0, **opts)
+    try:
+        announce("mr benchmark options", conn, opts)
+        g, _ = run(env, J, I, conn, ctx=ctx)
+    finally:
+        ctx.close()
+    assert np.array_equal(g, oracle.mr_fh(J, I, conn))
+
+
 def test_repeatable(env):
     J, I = synth.mr_inputs(700, 900, 13, n_disks=20, radius=(5, 20), offset=32)
     announce("mr repeat")
