@@ -108,6 +108,20 @@ def test_grid_size_does_not_change_bytes(env, pb):
         ctx.close()
 
 
+@pytest.mark.parametrize("conn,opts", [(8, dict(wg_waves=8)), (8, dict(stage_depth=1)), (4, dict(wg_waves=8, stage_depth=16))])
+def test_launch_options_do_not_change_bytes(env, conn, opts):
+    """Eight-wave workgroups and LDS stages of 1 and 16 items on a few hundred
+    26x26 tiles with ragged edges."""
+    torch, iw, _ = env
+    B = synth.edt_input(700, 533, seed=12, coverage=0.25)
+    ctx = iw.Context(0, **opts)
+    try:
+        announce("edt options", conn, opts)
+        check(env, B, conn, ctx)
+    finally:
+        ctx.close()
+
+
 def test_repeatable(env):
     B = synth.edt_input(600, 500, seed=8, coverage=0.3)
     announce("edt repeat")
