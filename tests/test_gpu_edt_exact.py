@@ -75,3 +75,24 @@ def test_exact_edt_random_small(env, h, w, p, seed):
     rng = np.random.default_rng(seed)
     B = (rng.random((h, w)) >= p).astype(np.uint8)
     check(B, *run(env, B))
+
+
+@pytest.mark.parametrize("h,w", [(3, 40000), (40000, 3)])
+def test_exact_edt_beyond_16_bit_sides(env, h, w):
+    """Sides above 32767: squared distances up to about 1.6e9, and (tall) 313
+    column segments whose nearest features come from far segments."""
+    B = np.ones((h, w), np.uint8)
+    rng = np.random.default_rng(h + w)
+    B[rng.integers(0, h, 4), rng.integers(0, w, 4)] = 0
+    announce("edt exact wide", h, w)
+    check(B, *run(env, B))
+
+
+def test_exact_edt_features_in_distant_segments_only(env):
+    """Each column's only features lie in its first and last 128-row segments,
+    so every segment in between takes its nearest feature from the carries."""
+    B = np.ones((1100, 70), np.uint8)
+    B[3, ::7] = 0
+    B[1090, 3::11] = 0
+    announce("edt exact distant segments")
+    check(B, *run(env, B))
